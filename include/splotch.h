@@ -1,0 +1,222 @@
+/*
+ * splotch.h -- C ABI of the MI355X Splotch renderer (libsplotch.so).
+ *
+ * The library renders a particle set into an RGB image the way Splotch
+ * defines it (Jin et al., ICCS 2010):
+ *   - Section 2: each particle is a Gaussian density rho0 exp(-r^2/sigma^2)
+ *     cut to zero for rays passing farther than f*sigma; r, g and b are
+ *     transported independently; along each ray dI/dx = (E_p - A_p I) rho_p(x)
+ *     (Eq. (1)); E_p and A_p follow a scalar through a colour look-up
+ *     table, and rho0 (the optical depth) may be scaled per particle.
+ *   - Section 3.2: per particle, normalise its values, transform it to
+ *     screen coordinates, assign its colour, find the pixels it affects and
+ *     combine all contributions into the image.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are HIP device pointers on the current
+ *     device; pointers marked "host" are ordinary host memory.  The caller
+ *     owns every buffer; the library keeps no reference after a call
+ *     returns and allocates no device memory of its own.
+ *   - Work is enqueued on params->stream (a hipStream_t; NULL = the null
+ *     stream) and the call returns without waiting for the image, except
+ *     that splotch_render reads back a few bytes (the pair total, the chunk
+ *     plan and, if requested, the statistics), which synchronises that
+ *     stream.
+ *   - Errors are reported through the return status; nothing is thrown.
+ *     Argument errors are detected on the host before any work is queued
+ *     and leave the image untouched.  Particles with non-finite fields,
+ *     h <= 0, a negative rho0 or an out-of-range species tag are not errors:
+ *     they are skipped and counted in the statistics.
+ *   - Calls on distinct streams with distinct workspaces may run
+ *     concurrently.
+ */
+#ifndef SPLOTCH_H
+#define SPLOTCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPLOTCH_OK = 0,
+    SPLOTCH_E_INVALID_ARG = 1, /* a host-checkable argument is wrong */
+    SPLOTCH_E_WORKSPACE = 2,   /* workspace missing or too small for n particles */
+    SPLOTCH_E_DEVICE = 3,      /* a HIP runtime call failed */
+    SPLOTCH_E_UNSUPPORTED = 4, /* valid but not supported (e.g. tile size) */
+    SPLOTCH_E_CAPACITY = 5     /* one particle needs more pair slots than the workspace holds */
+} splotch_status;
+
+enum { SPLOTCH_ORTHO = 0, SPLOTCH_PERSPECTIVE = 1 };
+enum { SPLOTCH_ADDITIVE = 0, SPLOTCH_ORDERED = 1 };
+
+#define SPLOTCH_MAX_SPECIES 8
+#define SPLOTCH_MAX_DIM 16384 /* maximum image width and height in pixels */
+
+/* Particle set, structure of arrays, all device pointers of n elements.
+ * x, y, z: world position; h: smoothing length (sigma = sigma_over_h * h);
+ * value: the scalar mapped to colour (Section 2, colour look-up table);
+ * rho0: optional density amplitude / optical-depth scale per particle
+ *       (Section 2, optical depth modulated by another scalar), NULL = 1;
+ * species: optional species tag per particle, NULL = species 0.
+ * n may be 0; n must be below 2^32. */
+typedef struct splotch_particles {
+    int64_t n;
+    const float *x, *y, *z;
+    const float *h;
+    const float *value;
+    const float *rho0;
+    const uint8_t *species;
+} splotch_particles;
+
+/* Camera (host struct).  right, up, fwd: orthonormal FP32 frame with
+ * right x up = fwd.  Camera coordinates of a point p are
+ * (p-eye).right, (p-eye).up, (p-eye).fwd = (xc, yc, zc).  Perspective:
+ * screen u = xc*F/zc + W/2, v = yc*F/zc + H/2, screen sigma = sigma*F/zc,
+ * with F = focal_px.  Orthographic: the same with F/zc replaced by
+ * px_per_unit.  Pixel (i, j) has its centre at (i + 1/2, j + 1/2); row 0
+ * is the bottom row.  Particles with zc outside (z_near, z_far] are culled
+ * whole.  The projection itself is evaluated in binary64 with the
+ * operation order given in the library source, so that visibility,
+ * bounding boxes and tile lists are reproducible bit for bit. */
+typedef struct splotch_camera {
+    int32_t projection; /* SPLOTCH_ORTHO or SPLOTCH_PERSPECTIVE */
+    int32_t width, height;
+    float eye[3], right[3], up[3], fwd[3];
+    float focal_px;    /* perspective only, > 0 */
+    float px_per_unit; /* orthographic only, > 0 */
+    float z_near, z_far;
+} splotch_camera;
+
+/* Colour look-up table (Section 2): n_entries >= 2 RGB triples, device,
+ * interleaved r,g,b, float32.  A normalised scalar t in [0,1] is mapped by
+ * linear interpolation at t*(n_entries-1). */
+typedef struct splotch_colourmap {
+    int32_t n_entries;
+    const float *rgb;
+} splotch_colourmap;
+
+/* Per-species colour and transfer settings.
+ * t = (g(value) - g(vmin)) / (g(vmax) - g(vmin)) clamped to [0,1] with
+ * g = log10 when log_scale (values <= 0 give t = 0) or the identity;
+ * vmin >= vmax asks the library for the exact min/max of the species'
+ * valid particles (positive ones only under log_scale).
+ * E_p = brightness * colour(t), A_p = absorption * colour(t) for ORDERED
+ * species and A_p = 0 for ADDITIVE species (Eq. (1)).  Absorption equal to
+ * brightness is the paper's recommended E = A setting. */
+typedef struct splotch_species {
+    float vmin, vmax;
+    int32_t log_scale;
+    float brightness;
+    float absorption;
+    int32_t mode; /* SPLOTCH_ADDITIVE or SPLOTCH_ORDERED */
+} splotch_species;
+
+/* Optional statistics (host struct), filled after the render. */
+typedef struct splotch_stats {
+    int64_t n_visible;      /* particles that touch at least one tile */
+    int64_t n_invalid;      /* non-finite fields, h <= 0, rho0 < 0, bad species */
+    int64_t n_depth_culled; /* zc outside (z_near, z_far] */
+    int64_t n_offscreen;    /* footprint box misses the screen */
+    int64_t n_pairs;        /* (tile, particle) pairs over all chunks */
+    int32_t n_chunks;       /* workspace-bounded passes */
+    int32_t tile;           /* tile edge used, in pixels */
+    int32_t ordered;        /* 1 if the depth-ordered path ran */
+    int32_t reserved;
+    float vmin[SPLOTCH_MAX_SPECIES], vmax[SPLOTCH_MAX_SPECIES]; /* ranges used */
+    /* Filled only when params->profile is set: milliseconds per stage,
+     * measured with HIP events on params->stream and summed over chunks:
+     * [0] value range + projection, [1] depth sort + reorder,
+     * [2] pair-offset scan, [3] pair emission, [4] tile sort + ranges,
+     * [5] splat; the number of (pixel, particle) contributions the splat
+     * composited, and how many of them came from absorbing particles. */
+    float stage_ms[6];
+    int64_t n_member_pairs;
+    int64_t n_member_absorbing;
+} splotch_stats;
+
+/* Render settings (host struct). */
+typedef struct splotch_params {
+    int32_t n_species; /* 1..SPLOTCH_MAX_SPECIES */
+    splotch_species species[SPLOTCH_MAX_SPECIES];
+    float sigma_over_h; /* sigma_p = sigma_over_h * h_p, > 0 (default 1) */
+    float trunc_f;      /* f: footprint radius f*sigma, > 0 (default 2) */
+    int32_t accumulate; /* 0: image = render; 1: composite over the image (it is
+                           the light entering from behind every particle) */
+    int32_t compensated; /* 1: compensated (Kahan) summation of emission */
+    int32_t tile;        /* tile edge in pixels: 0 (= 16), 8, 16 or 32 */
+    int32_t profile;     /* 1: time each stage (needs stats) */
+    void *stream;        /* hipStream_t */
+    void *workspace;     /* device, >= splotch_workspace_size() bytes, 256-aligned */
+    size_t workspace_bytes;
+    splotch_stats *stats; /* host, may be NULL */
+} splotch_params;
+
+/* Output image: planar float32 [3][height][width], device. */
+typedef struct splotch_image {
+    float *rgb;
+    int32_t width, height;
+} splotch_image;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *splotch_status_string(splotch_status s);
+
+/* Fill *cam with a camera at eye looking at `at` with the given up hint
+ * (host arrays of 3).  projection PERSPECTIVE: fov_or_scale is the
+ * horizontal field of view in degrees (0 < fov < 180); ORTHO: it is
+ * px_per_unit.  Returns SPLOTCH_E_INVALID_ARG for degenerate frames. */
+splotch_status splotch_camera_look_at(splotch_camera *cam, const float eye[3],
+                                      const float at[3], const float up[3],
+                                      int32_t projection, float fov_or_scale,
+                                      int32_t width, int32_t height, float z_near,
+                                      float z_far);
+
+/* Bytes of workspace needed to render n particles at the camera's size
+ * with room for max_pairs (tile, particle) pairs per pass (max_pairs <= 0
+ * picks 4n + 65536).  A render whose pairs exceed the capacity runs in
+ * several passes (chunks) over the same workspace.  Host only. */
+splotch_status splotch_workspace_size(int64_t n, const splotch_camera *cam,
+                                      const splotch_params *params, int64_t max_pairs,
+                                      size_t *bytes);
+
+/* Render particles into image (Section 2 model, Section 3.2 stages):
+ * project and cull, normalise and colour, bin each particle into the
+ * screen tiles its footprint box touches, order each tile's list by depth
+ * (front to back, ties by particle index) when any species is ORDERED,
+ * and composite every pixel.  Additive-only sets skip the depth order.
+ * All pointers in the structs are as documented above; image dimensions
+ * must equal the camera's. */
+splotch_status splotch_render(const splotch_particles *particles, const splotch_camera *cam,
+                              const splotch_colourmap *cmap, const splotch_params *params,
+                              splotch_image *image);
+
+/* Stage outputs for inspection and exact comparison (Section 3.2: the
+ * screen transform and footprint of each particle).  For every particle
+ * (device arrays of n): status (0 visible, 1 invalid, 2 depth-culled,
+ * 3 off-screen), bbox (4 int32: i0, i1, j0, j1 of its clipped pixel box),
+ * spec (3 float32: u - i0, v - j0, (f sigma_s)^2, the binary32 fields that
+ * decide pixel membership), depth key (uint32, monotone image of the
+ * binary32 camera depth) and tile count (uint32, for params->tile).  Any
+ * output pointer may be NULL.  Uses the workspace like splotch_render. */
+splotch_status splotch_project(const splotch_particles *particles, const splotch_camera *cam,
+                               const splotch_params *params, int8_t *status, int32_t *bbox,
+                               float *spec, uint32_t *key, uint32_t *ntiles);
+
+/* Binning outputs: the per-tile particle lists of one render pass, as the
+ * splat consumes them.  tile_start/tile_end (device, n_tiles uint32 each)
+ * bound each tile's slice of pair_particle (device, capacity max_out
+ * uint32), which lists particle indices tile by tile, front to back for
+ * depth-ordered renders and by index otherwise.  *n_pairs (host) receives
+ * the pair total; SPLOTCH_E_CAPACITY if it exceeds max_out or the
+ * workspace's pair capacity. */
+splotch_status splotch_bin(const splotch_particles *particles, const splotch_camera *cam,
+                           const splotch_params *params, uint32_t *tile_start,
+                           uint32_t *tile_end, uint32_t *pair_particle, int64_t max_out,
+                           int64_t *n_pairs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPLOTCH_H */

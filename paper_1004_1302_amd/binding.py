@@ -1,0 +1,349 @@
+"""Python binding of libsplotch (ctypes).
+
+Argument marshalling only: every stage of the render runs in the HIP
+library.  torch supplies device memory (particles, palette, image,
+workspace) and the stream.  If the library is missing this module raises;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsplotch.so")
+
+MAX_SPECIES = 8
+ORTHO, PERSPECTIVE = 0, 1
+ADDITIVE, ORDERED = 0, 1
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device", 4: "unsupported",
+          5: "capacity"}
+
+
+class SplotchError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {_lib().splotch_status_string(code).decode()} (status {code})")
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("h", C.c_void_p), ("value", C.c_void_p), ("rho0", C.c_void_p),
+                ("species", C.c_void_p)]
+
+
+class CameraS(C.Structure):
+    _fields_ = [("projection", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("eye", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3),
+                ("fwd", C.c_float * 3), ("focal_px", C.c_float), ("px_per_unit", C.c_float),
+                ("z_near", C.c_float), ("z_far", C.c_float)]
+
+
+class Colourmap(C.Structure):
+    _fields_ = [("n_entries", C.c_int32), ("rgb", C.c_void_p)]
+
+
+class SpeciesS(C.Structure):
+    _fields_ = [("vmin", C.c_float), ("vmax", C.c_float), ("log_scale", C.c_int32),
+                ("brightness", C.c_float), ("absorption", C.c_float), ("mode", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_visible", C.c_int64), ("n_invalid", C.c_int64),
+                ("n_depth_culled", C.c_int64), ("n_offscreen", C.c_int64),
+                ("n_pairs", C.c_int64), ("n_chunks", C.c_int32), ("tile", C.c_int32),
+                ("ordered", C.c_int32), ("reserved", C.c_int32),
+                ("vmin", C.c_float * MAX_SPECIES), ("vmax", C.c_float * MAX_SPECIES),
+                ("stage_ms", C.c_float * 6), ("n_member_pairs", C.c_int64),
+                ("n_member_absorbing", C.c_int64)]
+
+    STAGES = ("project", "depth_sort", "scan", "emit", "tile_sort", "splat")
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("vmin", "vmax", "reserved", "stage_ms")}
+        d["vmin"] = list(self.vmin)
+        d["vmax"] = list(self.vmax)
+        d["stage_ms"] = dict(zip(self.STAGES, list(self.stage_ms)))
+        return d
+
+
+class Params(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("species", SpeciesS * MAX_SPECIES),
+                ("sigma_over_h", C.c_float), ("trunc_f", C.c_float),
+                ("accumulate", C.c_int32), ("compensated", C.c_int32), ("tile", C.c_int32),
+                ("profile", C.c_int32), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats))]
+
+
+class Image(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+_L = None
+
+EXPORTS = ("splotch_status_string", "splotch_camera_look_at", "splotch_workspace_size",
+           "splotch_render", "splotch_project", "splotch_bin")
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libsplotch.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.splotch_status_string.restype = C.c_char_p
+        L.splotch_status_string.argtypes = [C.c_int]
+        L.splotch_camera_look_at.restype = C.c_int
+        L.splotch_camera_look_at.argtypes = [C.POINTER(CameraS), C.POINTER(C.c_float * 3),
+                                             C.POINTER(C.c_float * 3), C.POINTER(C.c_float * 3),
+                                             C.c_int32, C.c_float, C.c_int32, C.c_int32,
+                                             C.c_float, C.c_float]
+        L.splotch_workspace_size.restype = C.c_int
+        L.splotch_workspace_size.argtypes = [C.c_int64, C.POINTER(CameraS), C.POINTER(Params),
+                                             C.c_int64, C.POINTER(C.c_size_t)]
+        L.splotch_render.restype = C.c_int
+        L.splotch_render.argtypes = [C.POINTER(Particles), C.POINTER(CameraS),
+                                     C.POINTER(Colourmap), C.POINTER(Params), C.POINTER(Image)]
+        L.splotch_project.restype = C.c_int
+        L.splotch_project.argtypes = [C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Params),
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
+        L.splotch_bin.restype = C.c_int
+        L.splotch_bin.argtypes = [C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Params),
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                  C.POINTER(C.c_int64)]
+        _L = L
+    return _L
+
+
+def lib():
+    return _lib()
+
+
+def status_string(code: int) -> str:
+    return _lib().splotch_status_string(code).decode()
+
+
+def _check(code, where):
+    if code != 0:
+        raise SplotchError(code, where)
+
+
+# ---------------------------------------------------------------- structs
+def camera_struct(cam) -> CameraS:
+    """From any object with the splotch_camera fields (e.g. synth.Camera)."""
+    c = CameraS()
+    c.projection = int(cam.projection)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    for name in ("eye", "right", "up", "fwd"):
+        v = [float(t) for t in getattr(cam, name)]
+        getattr(c, name)[:] = v
+    c.focal_px = float(cam.focal_px)
+    c.px_per_unit = float(cam.px_per_unit)
+    c.z_near = float(cam.z_near)
+    c.z_far = float(cam.z_far)
+    return c
+
+
+def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near, z_far) -> CameraS:
+    c = CameraS()
+    f3 = C.c_float * 3
+    _check(_lib().splotch_camera_look_at(C.byref(c), C.byref(f3(*eye)), C.byref(f3(*at)),
+                                         C.byref(f3(*up)), projection, fov_or_scale, width,
+                                         height, z_near, z_far), "splotch_camera_look_at")
+    return c
+
+
+def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
+                  tile=0, profile=False) -> Params:
+    p = Params()
+    if not 1 <= len(species) <= MAX_SPECIES:
+        raise ValueError("1..8 species")
+    p.n_species = len(species)
+    for k, s in enumerate(species):
+        p.species[k] = SpeciesS(float(s.vmin), float(s.vmax), int(s.log_scale),
+                                float(s.brightness), float(s.absorption), int(s.mode))
+    p.sigma_over_h = float(sigma_over_h)
+    p.trunc_f = float(trunc_f)
+    p.accumulate = 1 if accumulate else 0
+    p.compensated = 1 if compensated else 0
+    p.tile = int(tile)
+    p.profile = 1 if profile else 0
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def particles_struct(parts: dict) -> Particles:
+    """parts: dict of contiguous device tensors x, y, z, h, value (float32)
+    and optional rho0 (float32), species (uint8)."""
+    import torch
+    P = Particles()
+    n = int(parts["x"].numel())
+    for k in ("x", "y", "z", "h", "value", "rho0"):
+        t = parts.get(k)
+        if t is not None:
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
+                raise ValueError(f"particle field {k} must be contiguous float32 of length {n}")
+    sp = parts.get("species")
+    if sp is not None and (sp.dtype != torch.uint8 or not sp.is_contiguous() or sp.numel() != n):
+        raise ValueError("species must be contiguous uint8")
+    P.n = n
+    P.x, P.y, P.z, P.h, P.value = (_ptr(parts[k]) for k in ("x", "y", "z", "h", "value"))
+    P.rho0 = _ptr(parts.get("rho0"))
+    P.species = _ptr(sp)
+    return P
+
+
+# ---------------------------------------------------------------- workspace
+_ws_cache: dict = {}
+
+
+def workspace_bytes(n, cam: CameraS, prm: Params, max_pairs=0) -> int:
+    out = C.c_size_t(0)
+    _check(_lib().splotch_workspace_size(int(n), C.byref(cam), C.byref(prm), int(max_pairs),
+                                         C.byref(out)), "splotch_workspace_size")
+    return int(out.value)
+
+
+def get_workspace(nbytes: int, device):
+    """A cached uint8 device tensor of at least nbytes (256-byte aligned)."""
+    import torch
+    key = str(device)
+    t = _ws_cache.get(key)
+    if t is None or t.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = t
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def release_workspace():
+    _ws_cache.clear()
+
+
+def _stream_ptr(device):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _setup(parts, cam, species, max_pairs, workspace, **kw):
+    P = particles_struct(parts)
+    cs = cam if isinstance(cam, CameraS) else camera_struct(cam)
+    prm = params_struct(species, **kw)
+    dev = parts["x"].device
+    if workspace is None:
+        need = workspace_bytes(P.n, cs, prm, max_pairs or 0)
+        workspace = get_workspace(need, dev)
+        nbytes = need  # the cached buffer may be larger; the pair capacity follows max_pairs
+    else:
+        nbytes = int(workspace.numel())
+    prm.workspace = C.c_void_p(workspace.data_ptr())
+    prm.workspace_bytes = nbytes
+    prm.stream = _stream_ptr(dev)
+    return P, cs, prm, dev
+
+
+def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, trunc_f=2.0,
+           accumulate=False, compensated=False, tile=0, max_pairs=0, workspace=None,
+           stats=False, profile=False):
+    """Render into image (planar float32 [3, H, W] device tensor; allocated
+    if None).  Returns the image, or (image, stats dict) with stats=True
+    (profile=True adds per-stage milliseconds to the stats)."""
+    import torch
+    P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
+                             trunc_f=trunc_f, accumulate=accumulate, compensated=compensated,
+                             tile=tile, profile=profile)
+    stats = stats or profile
+    if image is None:
+        image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)
+    if image.dtype != torch.float32 or not image.is_contiguous() or \
+            tuple(image.shape) != (3, cs.height, cs.width):
+        raise ValueError("image must be contiguous float32 [3, H, W]")
+    if palette.dtype != torch.float32 or not palette.is_contiguous() or palette.dim() != 2 \
+            or palette.shape[1] != 3:
+        raise ValueError("palette must be contiguous float32 [K, 3]")
+    cm = Colourmap(int(palette.shape[0]), C.c_void_p(palette.data_ptr()))
+    img = Image(C.c_void_p(image.data_ptr()), cs.width, cs.height)
+    st = Stats()
+    if stats:
+        prm.stats = C.pointer(st)
+    _check(_lib().splotch_render(C.byref(P), C.byref(cs), C.byref(cm), C.byref(prm),
+                                 C.byref(img)), "splotch_render")
+    return (image, st.as_dict()) if stats else image
+
+
+def project(parts: dict, cam, species, *, sigma_over_h=1.0, trunc_f=2.0, tile=0,
+            workspace=None):
+    """Per-particle stage outputs: dict of device tensors status (int8),
+    bbox (int32 [n,4]), spec (float32 [n,3]), key (uint32 as int32 view
+    bits), ntiles (uint32 bits in int32)."""
+    import torch
+    P, cs, prm, dev = _setup(parts, cam, species, 1, workspace, sigma_over_h=sigma_over_h,
+                             trunc_f=trunc_f, tile=tile)
+    n = P.n
+    out = dict(status=torch.empty(n, dtype=torch.int8, device=dev),
+               bbox=torch.empty((n, 4), dtype=torch.int32, device=dev),
+               spec=torch.empty((n, 3), dtype=torch.float32, device=dev),
+               key=torch.empty(n, dtype=torch.int32, device=dev),
+               ntiles=torch.empty(n, dtype=torch.int32, device=dev))
+    st = Stats()
+    prm.stats = C.pointer(st)
+    _check(_lib().splotch_project(C.byref(P), C.byref(cs), C.byref(prm), _ptr(out["status"]),
+                                  _ptr(out["bbox"]), _ptr(out["spec"]), _ptr(out["key"]),
+                                  _ptr(out["ntiles"])), "splotch_project")
+    out["stats"] = st.as_dict()
+    return out
+
+
+def bin_pairs(parts: dict, cam, species, *, sigma_over_h=1.0, trunc_f=2.0, tile=0,
+              max_pairs=0, workspace=None):
+    """Per-tile particle lists: (tile_start, tile_end, pair_particle) device
+    int32 tensors (uint32 bits) and the pair count."""
+    import torch
+    P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
+                             trunc_f=trunc_f, tile=tile)
+    T = tile or 16
+    nt = ((cs.width + T - 1) // T) * ((cs.height + T - 1) // T)
+    cap = max_pairs or (4 * P.n + 65536)
+    ts = torch.empty(nt, dtype=torch.int32, device=dev)
+    te = torch.empty(nt, dtype=torch.int32, device=dev)
+    pp = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    npairs = C.c_int64(0)
+    _check(_lib().splotch_bin(C.byref(P), C.byref(cs), C.byref(prm), _ptr(ts), _ptr(te),
+                              _ptr(pp), int(cap), C.byref(npairs)), "splotch_bin")
+    return ts, te, pp[: npairs.value], int(npairs.value)
+
+
+@dataclass
+class SpeciesParams:
+    vmin: float = 0.0
+    vmax: float = 0.0
+    log_scale: int = 0
+    brightness: float = 1.0
+    absorption: float = 0.0
+    mode: int = ADDITIVE
+
+
+def scene_to_device(scene, device="cuda"):
+    """Copy a host synth.Scene's particle arrays to device tensors."""
+    import torch
+
+    def t(a, dt):
+        return None if a is None else torch.from_numpy(a).to(device=device, dtype=dt).contiguous()
+    parts = dict(x=t(scene.x, torch.float32), y=t(scene.y, torch.float32),
+                 z=t(scene.z, torch.float32), h=t(scene.h, torch.float32),
+                 value=t(scene.value, torch.float32))
+    if scene.rho0 is not None:
+        parts["rho0"] = t(scene.rho0, torch.float32)
+    if scene.species is not None:
+        parts["species"] = t(scene.species, torch.uint8)
+    pal = torch.from_numpy(scene.palette).to(device=device, dtype=torch.float32).contiguous()
+    return parts, pal

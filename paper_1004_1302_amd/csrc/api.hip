@@ -1,0 +1,624 @@
+// Host side of libsplotch: argument validation, workspace layout, stage
+// orchestration on the caller's stream, chunking when the (tile, particle)
+// pairs exceed the workspace, and the C ABI declared in include/splotch.h.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/splotch.h"
+#include "internal.h"
+
+using namespace splotch;
+
+namespace {
+
+constexpr uint32_t kMaxChunks = 4096;
+constexpr uint64_t kMaxPairCap = 0xFFFF0000ull;  // pair indices are 32-bit
+
+struct Layout {
+    size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
+    size_t tstart, tend, mcount, pk0, pk1, pv0, pv1;
+    size_t total;
+    uint64_t pair_cap;
+    uint32_t n_tiles;
+    int ntx, nty, tile;
+    bool ordered;
+};
+
+int tile_of(const splotch_params *p) { return p->tile == 0 ? 16 : p->tile; }
+
+bool any_ordered(const splotch_params *p) {
+    for (int s = 0; s < p->n_species; ++s)
+        if (p->species[s].mode == SPLOTCH_ORDERED) return true;
+    return false;
+}
+
+// Lay out the workspace for n particles and pair capacity cap.
+Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uint64_t cap) {
+    Layout L;
+    memset(&L, 0, sizeof L);
+    L.tile = tile_of(p);
+    L.ntx = (cam->width + L.tile - 1) / L.tile;
+    L.nty = (cam->height + L.tile - 1) / L.tile;
+    L.n_tiles = (uint32_t)(L.ntx * L.nty);
+    L.ordered = any_ordered(p);
+    L.pair_cap = cap;
+    const size_t N = (size_t)n;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align_up(bytes ? bytes : 1, 256);
+        return at;
+    };
+    L.rec = take(N * sizeof(Rec));
+    L.cnt = take(N * 4);
+    if (L.ordered) {
+        L.key0 = take(N * 4);
+        L.key1 = take(N * 4);
+        L.val0 = take(N * 4);
+        L.val1 = take(N * 4);
+    }
+    L.off = take((N + 1) * 8);
+    L.scan = take(scan_u32_u64_scratch_bytes(N));
+    L.radix = take(radix_scratch_bytes(std::max<size_t>(L.ordered ? N : 0, (size_t)cap)));
+    L.counters = take(kCntN * 8);
+    L.range = take(2 * kMaxSpecies * 4);
+    L.bounds = take((2 + 2 * (kMaxChunks + 1)) * 8);
+    L.tstart = take((size_t)L.n_tiles * 4);
+    L.tend = take((size_t)L.n_tiles * 4);
+    L.mcount = take((size_t)L.n_tiles * 16);
+    L.pk0 = take(cap * 4);
+    L.pk1 = take(cap * 4);
+    L.pv0 = take(cap * 4);
+    L.pv1 = take(cap * 4);
+    L.total = o;
+    return L;
+}
+
+// Largest pair capacity whose layout fits in `bytes`.
+bool fit_capacity(int64_t n, const splotch_camera *cam, const splotch_params *p, size_t bytes,
+                  Layout *out) {
+    Layout L0 = layout(n, cam, p, 1);
+    if (L0.total > bytes) return false;
+    uint64_t lo = 1, hi = kMaxPairCap;
+    // per pair: 16 bytes plus about 0.26 bytes of radix scratch
+    uint64_t guess = (uint64_t)((bytes - L0.total) / 16.3);
+    hi = std::min<uint64_t>(hi, guess + 4096);
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo + 1) / 2;
+        if (layout(n, cam, p, mid).total <= bytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *out = layout(n, cam, p, lo);
+    return true;
+}
+
+bool finite3(const float *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+splotch_status validate_camera(const splotch_camera *c) {
+    if (!c) return SPLOTCH_E_INVALID_ARG;
+    if (c->projection != SPLOTCH_ORTHO && c->projection != SPLOTCH_PERSPECTIVE)
+        return SPLOTCH_E_INVALID_ARG;
+    if (c->width <= 0 || c->height <= 0 || c->width > SPLOTCH_MAX_DIM ||
+        c->height > SPLOTCH_MAX_DIM)
+        return SPLOTCH_E_INVALID_ARG;
+    if (!finite3(c->eye) || !finite3(c->right) || !finite3(c->up) || !finite3(c->fwd))
+        return SPLOTCH_E_INVALID_ARG;
+    const float *b[3] = {c->right, c->up, c->fwd};
+    for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 3; ++q) {
+            double d = (double)b[a][0] * b[q][0] + (double)b[a][1] * b[q][1] +
+                       (double)b[a][2] * b[q][2];
+            if (fabs(d - (a == q ? 1.0 : 0.0)) > 1e-5) return SPLOTCH_E_INVALID_ARG;
+        }
+    if (c->projection == SPLOTCH_PERSPECTIVE) {
+        if (!(c->focal_px > 0.0f) || !isfinite(c->focal_px)) return SPLOTCH_E_INVALID_ARG;
+        if (!(c->z_near > 0.0f)) return SPLOTCH_E_INVALID_ARG;
+    } else {
+        if (!(c->px_per_unit > 0.0f) || !isfinite(c->px_per_unit)) return SPLOTCH_E_INVALID_ARG;
+    }
+    if (isnan(c->z_near) || isnan(c->z_far) || !(c->z_far > c->z_near))
+        return SPLOTCH_E_INVALID_ARG;
+    return SPLOTCH_OK;
+}
+
+splotch_status validate_params(const splotch_params *p) {
+    if (!p) return SPLOTCH_E_INVALID_ARG;
+    if (p->n_species < 1 || p->n_species > SPLOTCH_MAX_SPECIES) return SPLOTCH_E_INVALID_ARG;
+    if (!(p->sigma_over_h > 0.0f) || !isfinite(p->sigma_over_h)) return SPLOTCH_E_INVALID_ARG;
+    if (!(p->trunc_f > 0.0f) || !isfinite(p->trunc_f)) return SPLOTCH_E_INVALID_ARG;
+    if (p->tile != 0 && p->tile != 8 && p->tile != 16 && p->tile != 32)
+        return SPLOTCH_E_UNSUPPORTED;
+    if (p->accumulate != 0 && p->accumulate != 1) return SPLOTCH_E_INVALID_ARG;
+    for (int s = 0; s < p->n_species; ++s) {
+        const splotch_species &q = p->species[s];
+        if (q.mode != SPLOTCH_ADDITIVE && q.mode != SPLOTCH_ORDERED) return SPLOTCH_E_INVALID_ARG;
+        if (!isfinite(q.brightness) || !isfinite(q.absorption) || q.absorption < 0.0f)
+            return SPLOTCH_E_INVALID_ARG;
+        if (isnan(q.vmin) || isnan(q.vmax)) return SPLOTCH_E_INVALID_ARG;
+        if (q.log_scale && q.vmin < q.vmax && !(q.vmin > 0.0f)) return SPLOTCH_E_INVALID_ARG;
+    }
+    return SPLOTCH_OK;
+}
+
+splotch_status validate_particles(const splotch_particles *P) {
+    if (!P || P->n < 0 || (uint64_t)P->n >= (1ull << 32)) return SPLOTCH_E_INVALID_ARG;
+    if (P->n > 0 && (!P->x || !P->y || !P->z || !P->h || !P->value)) return SPLOTCH_E_INVALID_ARG;
+    return SPLOTCH_OK;
+}
+
+CamDev cam_dev(const splotch_camera *c) {
+    CamDev d;
+    for (int k = 0; k < 3; ++k) {
+        d.eye[k] = c->eye[k];
+        d.right[k] = c->right[k];
+        d.up[k] = c->up[k];
+        d.fwd[k] = c->fwd[k];
+    }
+    d.focal = c->focal_px;
+    d.ppu = c->px_per_unit;
+    d.znear = c->z_near;
+    d.zfar = c->z_far;
+    d.half_w = 0.5 * (double)c->width;
+    d.half_h = 0.5 * (double)c->height;
+    d.wmax = (double)(c->width - 1);
+    d.hmax = (double)(c->height - 1);
+    d.persp = c->projection == SPLOTCH_PERSPECTIVE;
+    d.width = c->width;
+    d.height = c->height;
+    return d;
+}
+
+SpeciesDev species_dev(const splotch_params *p) {
+    SpeciesDev s;
+    memset(&s, 0, sizeof s);
+    s.n = p->n_species;
+    for (int k = 0; k < p->n_species; ++k) {
+        const splotch_species &q = p->species[k];
+        s.vmin[k] = q.vmin;
+        s.vmax[k] = q.vmax;
+        s.brightness[k] = q.brightness;
+        s.absorption[k] = q.absorption;
+        s.log_scale[k] = q.log_scale ? 1 : 0;
+        s.ordered[k] = q.mode == SPLOTCH_ORDERED;
+        s.auto_range[k] = !(q.vmin < q.vmax);
+    }
+    return s;
+}
+
+#define TRY(expr)                                      \
+    do {                                               \
+        if ((expr) != hipSuccess) return SPLOTCH_E_DEVICE; \
+    } while (0)
+
+// Stage timer: HIP events recorded on the render's stream between stages.
+struct Prof {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> stage;  // stage of the interval ending at ev[k]
+    hipError_t start(bool enable, hipStream_t st) {
+        on = enable;
+        s = st;
+        if (!on) return hipSuccess;
+        return mark(-1);
+    }
+    hipError_t mark(int stg) {
+        if (!on) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+        stage.push_back(stg);
+        return hipEventRecord(e, s);
+    }
+    // Sum intervals per stage (synchronises the stream).
+    hipError_t finish(float *ms, int nstages) {
+        if (!on) return hipSuccess;
+        hipError_t r = hipStreamSynchronize(s);
+        for (int k = 0; k < nstages; ++k) ms[k] = 0.0f;
+        for (size_t k = 1; k < ev.size() && r == hipSuccess; ++k) {
+            float t = 0.0f;
+            r = hipEventElapsedTime(&t, ev[k - 1], ev[k]);
+            if (stage[k] >= 0 && stage[k] < nstages) ms[stage[k]] += t;
+        }
+        return r;
+    }
+    ~Prof() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+struct Ctx {
+    Layout L;
+    char *ws;
+    hipStream_t s;
+    Prof prof;
+    template <typename T>
+    T *at(size_t off) const {
+        return reinterpret_cast<T *>(ws + off);
+    }
+};
+
+// Stage 1: auto value ranges + projection.  Fills rec, cnt, key0 (if ordered).
+splotch_status run_project(const Ctx &c, const splotch_particles *P, const splotch_camera *cam,
+                           const splotch_params *p, int8_t *o_status, int32_t *o_bbox,
+                           float *o_spec, uint32_t *o_key) {
+    ProjectArgs a;
+    memset(&a, 0, sizeof a);
+    a.cam = cam_dev(cam);
+    a.sp = species_dev(p);
+    a.x = P->x;
+    a.y = P->y;
+    a.z = P->z;
+    a.h = P->h;
+    a.value = P->value;
+    a.rho0 = P->rho0;
+    a.species = P->species;
+    a.n = P->n;
+    a.soh = (double)p->sigma_over_h;
+    a.f = (double)p->trunc_f;
+    a.tile = c.L.tile;
+    a.rec = c.at<Rec>(c.L.rec);
+    a.cnt = c.at<uint32_t>(c.L.cnt);
+    a.key = c.L.ordered ? c.at<uint32_t>(c.L.key0) : nullptr;
+    a.counters = c.at<unsigned long long>(c.L.counters);
+    a.o_status = o_status;
+    a.o_bbox = o_bbox;
+    a.o_spec = o_spec;
+    a.o_key = o_key;
+    TRY(launch_fill_u32(c.at<uint32_t>(c.L.counters), 0u, 2 * kCntN, c.s));
+    uint32_t *range = c.at<uint32_t>(c.L.range);
+    TRY(launch_value_range(a, range, c.s));
+    a.range_bits = range;
+    TRY(launch_project(a, c.s));
+    TRY(const_cast<Prof &>(c.prof).mark(0));
+    return SPLOTCH_OK;
+}
+
+// Stage 2: processing order (depth sort when ordered) and pair offsets.
+// Returns pointers to the order (or null) and the counts in that order.
+splotch_status run_order_and_scan(const Ctx &c, int64_t n, const uint32_t **order,
+                                  const uint32_t **cnt_proc) {
+    uint32_t *cnt = c.at<uint32_t>(c.L.cnt);
+    *order = nullptr;
+    *cnt_proc = cnt;
+    if (c.L.ordered && n > 0) {
+        bool in1 = false;
+        uint32_t *k0 = c.at<uint32_t>(c.L.key0), *k1 = c.at<uint32_t>(c.L.key1);
+        uint32_t *v0 = c.at<uint32_t>(c.L.val0), *v1 = c.at<uint32_t>(c.L.val1);
+        TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, 32, false,
+                             c.at<void>(c.L.radix), &in1, c.s));
+        const uint32_t *ord = in1 ? v1 : v0;
+        // key buffers are free after the sort: counts in processing order
+        TRY(launch_gather_u32(cnt, ord, k0, (size_t)n, c.s));
+        *order = ord;
+        *cnt_proc = k0;
+    }
+    TRY(const_cast<Prof &>(c.prof).mark(1));
+    TRY(launch_scan_u32_u64(*cnt_proc, c.at<uint64_t>(c.L.off), (size_t)n, c.at<void>(c.L.scan),
+                            c.s));
+    TRY(const_cast<Prof &>(c.prof).mark(2));
+    return SPLOTCH_OK;
+}
+
+// Bin one chunk [first, last) of processing positions: emit, sort by tile,
+// tile ranges.  Returns the sorted pair values via *vals.
+splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t *cnt_proc,
+                             uint64_t first, uint64_t last, uint64_t off_first, uint64_t npairs,
+                             const uint32_t **vals) {
+    uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
+    uint32_t *pv0 = c.at<uint32_t>(c.L.pv0), *pv1 = c.at<uint32_t>(c.L.pv1);
+    EmitArgs e;
+    e.rec = c.at<Rec>(c.L.rec);
+    e.order = order;
+    e.cnt = cnt_proc;
+    e.off = c.at<uint64_t>(c.L.off);
+    e.first = first;
+    e.last = last;
+    e.base = off_first;
+    e.tile = c.L.tile;
+    e.ntx = c.L.ntx;
+    e.pair_key = pk0;
+    e.pair_val = pv0;
+    TRY(launch_emit(e, c.s));
+    TRY(const_cast<Prof &>(c.prof).mark(3));
+    int bits = 0;
+    while ((1ull << bits) < (uint64_t)c.L.n_tiles) ++bits;
+    bool in1 = false;
+    TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)npairs, bits, true,
+                         c.at<void>(c.L.radix), &in1, c.s));
+    const uint32_t *keys = in1 ? pk1 : pk0;
+    *vals = in1 ? pv1 : pv0;
+    TRY(launch_tile_ranges(keys, (size_t)npairs, c.at<uint32_t>(c.L.tstart),
+                           c.at<uint32_t>(c.L.tend), c.L.n_tiles, c.s));
+    TRY(const_cast<Prof &>(c.prof).mark(4));
+    return SPLOTCH_OK;
+}
+
+// Read the pair total and plan chunks.  plan receives (position, offset)
+// boundaries: chunk k covers [plan[2k], plan[2k+2]).
+splotch_status plan_chunks(const Ctx &c, int64_t n, std::vector<uint64_t> *plan) {
+    uint64_t total = 0;
+    uint64_t *off = c.at<uint64_t>(c.L.off);
+    TRY(hipMemcpyAsync(&total, off + n, 8, hipMemcpyDeviceToHost, c.s));
+    TRY(hipStreamSynchronize(c.s));
+    plan->clear();
+    if (total <= c.L.pair_cap) {
+        *plan = {0, 0, (uint64_t)n, total};
+        return SPLOTCH_OK;
+    }
+    uint64_t *bounds = c.at<uint64_t>(c.L.bounds);
+    TRY(launch_chunk_plan(off, (uint64_t)n, c.L.pair_cap, bounds, kMaxChunks, c.s));
+    std::vector<uint64_t> hb(2 + 2 * (kMaxChunks + 1));
+    TRY(hipMemcpyAsync(hb.data(), bounds, hb.size() * 8, hipMemcpyDeviceToHost, c.s));
+    TRY(hipStreamSynchronize(c.s));
+    if (hb[1] != 0) return SPLOTCH_E_CAPACITY;
+    const uint64_t nch = hb[0];
+    plan->assign(hb.begin() + 2, hb.begin() + 2 + 2 * (nch + 1));
+    return SPLOTCH_OK;
+}
+
+splotch_status read_stats(Ctx &c, const splotch_params *p, int64_t pairs, int chunks) {
+    if (!p->stats) return SPLOTCH_OK;
+    float stage_ms[6] = {0, 0, 0, 0, 0, 0};
+    TRY(c.prof.finish(stage_ms, 6));
+    int64_t members = 0, absorbing = 0;
+    if (c.prof.on) {
+        std::vector<unsigned long long> mc(2 * (size_t)c.L.n_tiles);
+        TRY(hipMemcpyAsync(mc.data(), c.at<void>(c.L.mcount), mc.size() * 8,
+                           hipMemcpyDeviceToHost, c.s));
+        TRY(hipStreamSynchronize(c.s));
+        for (size_t k = 0; k < mc.size(); k += 2) {
+            members += (int64_t)mc[k];
+            absorbing += (int64_t)mc[k + 1];
+        }
+    }
+    unsigned long long cnt[kCntN];
+    uint32_t range[2 * kMaxSpecies];
+    TRY(hipMemcpyAsync(cnt, c.at<void>(c.L.counters), sizeof cnt, hipMemcpyDeviceToHost, c.s));
+    TRY(hipMemcpyAsync(range, c.at<void>(c.L.range), sizeof range, hipMemcpyDeviceToHost, c.s));
+    TRY(hipStreamSynchronize(c.s));
+    splotch_stats *st = p->stats;
+    memset(st, 0, sizeof *st);
+    st->n_visible = (int64_t)cnt[kCntVisible];
+    st->n_invalid = (int64_t)cnt[kCntInvalid];
+    st->n_depth_culled = (int64_t)cnt[kCntDepth];
+    st->n_offscreen = (int64_t)cnt[kCntOffscreen];
+    st->n_pairs = pairs;
+    st->n_chunks = chunks;
+    st->tile = c.L.tile;
+    st->ordered = c.L.ordered ? 1 : 0;
+    for (int k = 0; k < 6; ++k) st->stage_ms[k] = stage_ms[k];
+    st->n_member_pairs = members;
+    st->n_member_absorbing = absorbing;
+    for (int s = 0; s < p->n_species; ++s) {
+        const splotch_species &q = p->species[s];
+        if (q.vmin < q.vmax) {
+            st->vmin[s] = q.vmin;
+            st->vmax[s] = q.vmax;
+        } else if (range[2 * s] == 0xFFFFFFFFu) {
+            st->vmin[s] = st->vmax[s] = 0.0f;
+        } else {
+            for (int w = 0; w < 2; ++w) {
+                uint32_t k = range[2 * s + w];
+                uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+                float f;
+                memcpy(&f, &b, 4);
+                (w ? st->vmax : st->vmin)[s] = f;
+            }
+        }
+    }
+    return SPLOTCH_OK;
+}
+
+splotch_status prepare(const splotch_particles *P, const splotch_camera *cam,
+                       const splotch_params *p, Ctx *c) {
+    splotch_status st;
+    if ((st = validate_particles(P)) != SPLOTCH_OK) return st;
+    if ((st = validate_camera(cam)) != SPLOTCH_OK) return st;
+    if ((st = validate_params(p)) != SPLOTCH_OK) return st;
+    if (!p->workspace || (reinterpret_cast<uintptr_t>(p->workspace) & 255u) != 0)
+        return SPLOTCH_E_WORKSPACE;
+    if (!fit_capacity(P->n, cam, p, p->workspace_bytes, &c->L)) return SPLOTCH_E_WORKSPACE;
+    c->ws = reinterpret_cast<char *>(p->workspace);
+    c->s = reinterpret_cast<hipStream_t>(p->stream);
+    if (c->prof.start(p->profile != 0 && p->stats != nullptr, c->s) != hipSuccess)
+        return SPLOTCH_E_DEVICE;
+    return SPLOTCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *splotch_status_string(splotch_status s) {
+    switch (s) {
+        case SPLOTCH_OK: return "ok";
+        case SPLOTCH_E_INVALID_ARG: return "invalid argument";
+        case SPLOTCH_E_WORKSPACE: return "workspace missing, misaligned or too small";
+        case SPLOTCH_E_DEVICE: return "HIP runtime error";
+        case SPLOTCH_E_UNSUPPORTED: return "unsupported setting";
+        case SPLOTCH_E_CAPACITY: return "a particle needs more pair slots than the workspace holds";
+    }
+    return "unknown status";
+}
+
+splotch_status splotch_camera_look_at(splotch_camera *cam, const float eye[3], const float at[3],
+                                      const float up[3], int32_t projection, float fov_or_scale,
+                                      int32_t width, int32_t height, float z_near, float z_far) {
+    if (!cam || !eye || !at || !up) return SPLOTCH_E_INVALID_ARG;
+    double f[3], r[3], u[3];
+    for (int k = 0; k < 3; ++k) f[k] = (double)at[k] - (double)eye[k];
+    double nf = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(nf > 0.0) || !isfinite(nf)) return SPLOTCH_E_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) f[k] /= nf;
+    // right = up x fwd, up' = fwd x right  (right x up' = fwd)
+    r[0] = (double)up[1] * f[2] - (double)up[2] * f[1];
+    r[1] = (double)up[2] * f[0] - (double)up[0] * f[2];
+    r[2] = (double)up[0] * f[1] - (double)up[1] * f[0];
+    double nr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(nr > 1e-12) || !isfinite(nr)) return SPLOTCH_E_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) r[k] /= nr;
+    u[0] = f[1] * r[2] - f[2] * r[1];
+    u[1] = f[2] * r[0] - f[0] * r[2];
+    u[2] = f[0] * r[1] - f[1] * r[0];
+    splotch_camera c;
+    memset(&c, 0, sizeof c);
+    c.projection = projection;
+    c.width = width;
+    c.height = height;
+    for (int k = 0; k < 3; ++k) {
+        c.eye[k] = eye[k];
+        c.right[k] = (float)r[k];
+        c.up[k] = (float)u[k];
+        c.fwd[k] = (float)f[k];
+    }
+    if (projection == SPLOTCH_PERSPECTIVE) {
+        if (!(fov_or_scale > 0.0f && fov_or_scale < 180.0f)) return SPLOTCH_E_INVALID_ARG;
+        c.focal_px = (float)((0.5 * width) / tan(0.5 * (double)fov_or_scale * M_PI / 180.0));
+    } else if (projection == SPLOTCH_ORTHO) {
+        c.px_per_unit = fov_or_scale;
+    } else {
+        return SPLOTCH_E_INVALID_ARG;
+    }
+    c.z_near = z_near;
+    c.z_far = z_far;
+    splotch_status st = validate_camera(&c);
+    if (st != SPLOTCH_OK) return st;
+    *cam = c;
+    return SPLOTCH_OK;
+}
+
+splotch_status splotch_workspace_size(int64_t n, const splotch_camera *cam,
+                                      const splotch_params *params, int64_t max_pairs,
+                                      size_t *bytes) {
+    if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32)) return SPLOTCH_E_INVALID_ARG;
+    splotch_status st;
+    if ((st = validate_camera(cam)) != SPLOTCH_OK) return st;
+    if ((st = validate_params(params)) != SPLOTCH_OK) return st;
+    uint64_t cap = max_pairs > 0 ? (uint64_t)max_pairs : 4ull * (uint64_t)n + 65536ull;
+    if (cap > kMaxPairCap) cap = kMaxPairCap;
+    *bytes = layout(n, cam, params, cap).total;
+    return SPLOTCH_OK;
+}
+
+splotch_status splotch_render(const splotch_particles *P, const splotch_camera *cam,
+                              const splotch_colourmap *cmap, const splotch_params *p,
+                              splotch_image *img) {
+    Ctx c;
+    splotch_status st = prepare(P, cam, p, &c);
+    if (st != SPLOTCH_OK) return st;
+    if (!cmap || cmap->n_entries < 2 || !cmap->rgb) return SPLOTCH_E_INVALID_ARG;
+    if (!img || !img->rgb || img->width != cam->width || img->height != cam->height)
+        return SPLOTCH_E_INVALID_ARG;
+    const int64_t n = P->n;
+    if ((st = run_project(c, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
+        return st;
+    const uint32_t *order, *cnt_proc;
+    if ((st = run_order_and_scan(c, n, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+    std::vector<uint64_t> plan;
+    if ((st = plan_chunks(c, n, &plan)) != SPLOTCH_OK) return st;
+    const int nch = (int)(plan.size() / 2) - 1;
+
+    SplatArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.rec = c.at<Rec>(c.L.rec);
+    sa.tile_start = c.at<uint32_t>(c.L.tstart);
+    sa.tile_end = c.at<uint32_t>(c.L.tend);
+    sa.palette = cmap->rgb;
+    sa.n_pal = cmap->n_entries;
+    sa.sp = species_dev(p);
+    sa.image = img->rgb;
+    sa.width = cam->width;
+    sa.height = cam->height;
+    sa.tile = c.L.tile;
+    sa.ntx = c.L.ntx;
+    sa.nty = c.L.nty;
+    sa.compensated = p->compensated ? 1 : 0;
+    sa.ordered = c.L.ordered ? 1 : 0;
+    sa.member_count = c.at<unsigned long long>(c.L.mcount);
+    TRY(launch_fill_u32(c.at<uint32_t>(c.L.mcount), 0u, (size_t)c.L.n_tiles * 4, c.s));
+
+    const uint64_t total = plan.back();
+    if (total == 0) {
+        // nothing on screen: the splat still writes every pixel
+        TRY(launch_fill_u32(c.at<uint32_t>(c.L.tstart), 0u, c.L.n_tiles, c.s));
+        TRY(launch_fill_u32(c.at<uint32_t>(c.L.tend), 0u, c.L.n_tiles, c.s));
+        sa.pair_val = c.at<uint32_t>(c.L.pv0);
+        sa.accumulate = p->accumulate;
+        TRY(launch_splat(sa, c.s));
+        TRY(c.prof.mark(5));
+        return read_stats(c, p, 0, 0);
+    }
+    // depth-ordered chunks are depth slabs: composite back to front
+    for (int q = 0; q < nch; ++q) {
+        const int k = c.L.ordered ? nch - 1 - q : q;
+        const uint64_t first = plan[2 * k], last = plan[2 * k + 2];
+        const uint64_t o0 = plan[2 * k + 1], o1 = plan[2 * k + 3];
+        const uint32_t *vals;
+        if ((st = run_bin_chunk(c, order, cnt_proc, first, last, o0, o1 - o0, &vals)) !=
+            SPLOTCH_OK)
+            return st;
+        sa.pair_val = vals;
+        sa.accumulate = q == 0 ? p->accumulate : 1;
+        TRY(launch_splat(sa, c.s));
+        TRY(c.prof.mark(5));
+    }
+    return read_stats(c, p, (int64_t)total, nch);
+}
+
+splotch_status splotch_project(const splotch_particles *P, const splotch_camera *cam,
+                               const splotch_params *p, int8_t *status, int32_t *bbox,
+                               float *spec, uint32_t *key, uint32_t *ntiles) {
+    Ctx c;
+    splotch_status st = prepare(P, cam, p, &c);
+    if (st != SPLOTCH_OK) return st;
+    if ((st = run_project(c, P, cam, p, status, bbox, spec, key)) != SPLOTCH_OK) return st;
+    if (ntiles && P->n > 0)
+        TRY(hipMemcpyAsync(ntiles, c.at<void>(c.L.cnt), (size_t)P->n * 4,
+                           hipMemcpyDeviceToDevice, c.s));
+    return read_stats(c, p, 0, 0);
+}
+
+splotch_status splotch_bin(const splotch_particles *P, const splotch_camera *cam,
+                           const splotch_params *p, uint32_t *tile_start, uint32_t *tile_end,
+                           uint32_t *pair_particle, int64_t max_out, int64_t *n_pairs) {
+    Ctx c;
+    splotch_status st = prepare(P, cam, p, &c);
+    if (st != SPLOTCH_OK) return st;
+    if (!tile_start || !tile_end || !pair_particle || !n_pairs || max_out < 0)
+        return SPLOTCH_E_INVALID_ARG;
+    const int64_t n = P->n;
+    if ((st = run_project(c, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
+        return st;
+    const uint32_t *order, *cnt_proc;
+    if ((st = run_order_and_scan(c, n, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+    uint64_t total = 0;
+    TRY(hipMemcpyAsync(&total, c.at<uint64_t>(c.L.off) + n, 8, hipMemcpyDeviceToHost, c.s));
+    TRY(hipStreamSynchronize(c.s));
+    *n_pairs = (int64_t)total;
+    if (total > c.L.pair_cap || total > (uint64_t)max_out) return SPLOTCH_E_CAPACITY;
+    const uint32_t *vals = c.at<uint32_t>(c.L.pv0);
+    if (total > 0) {
+        if ((st = run_bin_chunk(c, order, cnt_proc, 0, (uint64_t)n, 0, total, &vals)) !=
+            SPLOTCH_OK)
+            return st;
+    } else {
+        TRY(launch_fill_u32(c.at<uint32_t>(c.L.tstart), 0u, c.L.n_tiles, c.s));
+        TRY(launch_fill_u32(c.at<uint32_t>(c.L.tend), 0u, c.L.n_tiles, c.s));
+    }
+    TRY(hipMemcpyAsync(tile_start, c.at<void>(c.L.tstart), (size_t)c.L.n_tiles * 4,
+                       hipMemcpyDeviceToDevice, c.s));
+    TRY(hipMemcpyAsync(tile_end, c.at<void>(c.L.tend), (size_t)c.L.n_tiles * 4,
+                       hipMemcpyDeviceToDevice, c.s));
+    if (total > 0)
+        TRY(hipMemcpyAsync(pair_particle, vals, (size_t)total * 4, hipMemcpyDeviceToDevice, c.s));
+    return read_stats(c, p, (int64_t)total, 1);
+}
+
+}  // extern "C"

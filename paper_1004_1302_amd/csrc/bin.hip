@@ -1,0 +1,128 @@
+// Screen-tile binning: each visible particle emits one (tile, particle)
+// pair per tile its footprint box touches (Section 3.2: the screen area a
+// particle affects; the paper's split of large particles into pixel
+// subsets becomes this per-tile duplication).  Pairs are emitted in
+// processing order (particle index, or front-to-back depth order), so a
+// stable sort by tile leaves every tile's list in that order.
+#include "internal.h"
+
+namespace splotch {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, size_t n) {
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        dst[k] = src[idx[k]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
+    const uint64_t k = a.first + (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (k >= a.last) return;
+    const uint32_t c = a.cnt[k];
+    if (c == 0) return;
+    const uint32_t i = a.order ? a.order[k] : (uint32_t)k;
+    const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
+    const int T = a.tile;
+    const int tx0 = (int)(bb.x & kBboxMask) / T, tx1 = (int)((bb.x >> kBboxBits) & kBboxMask) / T;
+    const int ty0 = (int)(bb.y & kBboxMask) / T, ty1 = (int)((bb.y >> kBboxBits) & kBboxMask) / T;
+    uint64_t o = a.off[k] - a.base;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            a.pair_key[o] = (uint32_t)(ty * a.ntx + tx);
+            a.pair_val[o] = i;
+            ++o;
+        }
+}
+
+__global__ void k_tile_ranges(const uint32_t *keys, size_t n, uint32_t *start, uint32_t *end) {
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        uint32_t key = keys[p];
+        if (p == 0 || keys[p - 1] != key) start[key] = (uint32_t)p;
+        if (p == n - 1 || keys[p + 1] != key) end[key] = (uint32_t)(p + 1);
+    }
+}
+
+// Greedy chunk plan over the pair offsets: chunk c covers processing
+// positions [bounds[2c], bounds[2c+2]) with pair offsets bounds[2c+1] ...
+// Layout: bounds[0] = number of chunks, bounds[1] = 1 if one particle
+// alone exceeds the capacity; then pairs (position, offset) for each
+// boundary starting at (0, 0).
+__global__ void k_chunk_plan(const uint64_t *off, uint64_t n, uint64_t cap, uint64_t *bounds,
+                             uint32_t max_chunks) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t b = 0;
+    uint32_t c = 0;
+    bounds[1] = 0;
+    bounds[2] = 0;
+    bounds[3] = off[0];
+    while (b < n && c < max_chunks) {
+        const uint64_t target = off[b] + cap;
+        uint64_t lo = b, hi = n;  // invariant: off[lo] <= target
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (off[mid] <= target)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        if (lo == b) {
+            bounds[1] = 1;
+            break;
+        }
+        ++c;
+        bounds[2 + 2 * c] = lo;
+        bounds[3 + 2 * c] = off[lo];
+        b = lo;
+    }
+    if (b < n && bounds[1] == 0) bounds[1] = 2;  // ran out of chunk slots
+    bounds[0] = c;
+}
+
+unsigned grid_for(size_t n, unsigned cap) {
+    size_t g = (n + kThreads - 1) / kThreads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, size_t n,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(n, 1u << 20)), dim3(kThreads), 0, s, src, idx,
+                       dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
+    const uint64_t n = a.last - a.first;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs, uint32_t *start,
+                              uint32_t *end, uint32_t n_tiles, hipStream_t s) {
+    hipError_t e = launch_fill_u32(start, 0u, n_tiles, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(end, 0u, n_tiles, s);
+    if (e != hipSuccess || n_pairs == 0) return e;
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(n_pairs, 1u << 20)), dim3(kThreads), 0, s,
+                       sorted_keys, n_pairs, start, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_plan(const uint64_t *off, uint64_t n, uint64_t capacity, uint64_t *bounds,
+                             uint32_t max_chunks, hipStream_t s) {
+    hipLaunchKernelGGL(k_chunk_plan, dim3(1), dim3(64), 0, s, off, n, capacity, bounds,
+                       max_chunks);
+    return hipGetLastError();
+}
+
+}  // namespace splotch

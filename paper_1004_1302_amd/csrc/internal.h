@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP translation units of libsplotch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace splotch {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kBboxBits = 14;  // i0, i1 packed in 14 bits each (W, H <= 16384)
+constexpr uint32_t kBboxMask = (1u << kBboxBits) - 1u;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
+// Status codes written per particle by the projection kernel.
+enum : int8_t { kVisible = 0, kInvalid = 1, kDepthCulled = 2, kOffscreen = 3 };
+
+// Camera promoted to binary64 on the host (exact: every FP32 value is a
+// binary64 value).
+struct CamDev {
+    double eye[3], right[3], up[3], fwd[3];
+    double focal, ppu, znear, zfar;
+    double half_w, half_h, wmax, hmax;  // W/2, H/2, W-1, H-1
+    int persp, width, height;
+};
+
+// Per-species settings as the kernels see them.
+struct SpeciesDev {
+    float vmin[kMaxSpecies], vmax[kMaxSpecies];
+    float brightness[kMaxSpecies], absorption[kMaxSpecies];
+    int log_scale[kMaxSpecies], ordered[kMaxSpecies], auto_range[kMaxSpecies];
+    int n;
+};
+
+// Projected particle record: 32 bytes, two uint4.
+//   a.x = i0 | i1 << 14 | species << 28     a.y = j0 | j1 << 14
+//   a.z = float(u - i0)                     a.w = float(v - j0)
+//   b.x = float((f sigma_s)^2)              b.y = float(log2(e) / sigma_s^2)
+//   b.z = t (normalised value)              b.w = rho0
+struct Rec {
+    uint4 a, b;
+};
+
+// Counters accumulated by the projection kernel (device, 64-bit).
+enum { kCntVisible = 0, kCntInvalid, kCntDepth, kCntOffscreen, kCntN };
+
+struct ProjectArgs {
+    CamDev cam;
+    SpeciesDev sp;
+    const float *x, *y, *z, *h, *value, *rho0;
+    const uint8_t *species;
+    int64_t n;
+    double soh, f;
+    int tile;
+    const uint32_t *range_bits;  // [2*kMaxSpecies] ordered bits of auto min/max, or null
+    Rec *rec;
+    uint32_t *cnt;   // tile count per particle
+    uint32_t *key;   // depth key per particle (kEmptyKey when not visible), may be null
+    unsigned long long *counters;  // [kCntN]
+    // optional stage outputs
+    int8_t *o_status;
+    int32_t *o_bbox;
+    float *o_spec;
+    uint32_t *o_key;
+};
+
+// ---- launchers (one per kernel family) ------------------------------------
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
+hipError_t launch_value_range(const ProjectArgs &a, uint32_t *range_bits, hipStream_t s);
+hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
+
+// Exclusive scan of n uint32 counts into n+1 uint64 offsets (out[n] = total).
+size_t scan_u32_u64_scratch_bytes(size_t n);
+hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void *scratch,
+                               hipStream_t s);
+// In-place exclusive scan of n uint32 values.
+size_t scan_u32_scratch_bytes(size_t n);
+hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+// vals_in may be null (values = 0..n-1).  Buffers k0/v0 hold the input;
+// k1/v1 are the second half of the ping-pong.  *result_in_1 tells which
+// half holds the output.  keys_needed = false lets the last pass skip
+// writing keys.
+size_t radix_scratch_bytes(size_t n);
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                            bool vals_identity, size_t n, int bits, bool keys_needed,
+                            void *scratch, bool *result_in_1, hipStream_t s);
+
+// Binning.
+hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst,
+                             size_t n, hipStream_t s);
+struct EmitArgs {
+    const Rec *rec;
+    const uint32_t *order;   // processing order -> particle index (null = identity)
+    const uint32_t *cnt;     // tile count in processing order
+    const uint64_t *off;     // pair offsets in processing order
+    uint64_t first, last;    // processing positions [first, last)
+    uint64_t base;           // off[first]
+    int tile, ntx;
+    uint32_t *pair_key, *pair_val;
+};
+hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs, uint32_t *start,
+                              uint32_t *end, uint32_t n_tiles, hipStream_t s);
+hipError_t launch_chunk_plan(const uint64_t *off, uint64_t n, uint64_t capacity,
+                             uint64_t *bounds, uint32_t max_chunks, hipStream_t s);
+
+// Splat.
+struct SplatArgs {
+    const Rec *rec;
+    const uint32_t *pair_val;
+    const uint32_t *tile_start, *tile_end;
+    const float *palette;
+    int n_pal;
+    SpeciesDev sp;
+    float *image;
+    unsigned long long *member_count;  // [2 per tile]: all, absorbing; summed over chunks
+    int width, height, tile, ntx, nty;
+    int accumulate, compensated, ordered;
+};
+hipError_t launch_splat(const SplatArgs &a, hipStream_t s);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace splotch

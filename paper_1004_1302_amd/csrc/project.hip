@@ -1,0 +1,312 @@
+// Per-particle stage of the render (Section 3.2: normalise, transform to
+// screen coordinates, find the affected screen area): one coalesced pass
+// over the structure-of-arrays particle set that writes a 32-byte record,
+// the number of screen tiles the footprint box touches and the depth key.
+//
+// The integer decisions follow a fixed recipe of IEEE operations so that
+// any conforming implementation reproduces them bit for bit:
+//   binary64, no contraction:
+//     d = p - eye;  xc = (d0 r0 + d1 r1) + d2 r2  (same for yc with up, zc with fwd)
+//     cull unless z_near < zc <= z_far
+//     s = F / zc (perspective) or px_per_unit (orthographic)
+//     u = xc s + W/2,  v = yc s + H/2,  sigma_s = (h * sigma_over_h) * s,  r = f sigma_s
+//     i0 = max(ceil((u - r) - 1/2), 0),  i1 = min(floor((u + r) - 1/2), W-1)  (same for j)
+//     off-screen unless i0 <= i1 and j0 <= j1
+//   binary32 rounding: u - i0, v - j0, r^2 (membership fields), zc (depth key).
+// Colour normalisation and the kernel scale are continuous values computed
+// in binary32 and are not part of the recipe.
+#include "internal.h"
+
+#include <float.h>
+
+namespace splotch {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t order_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ float from_order_bits(uint32_t k) {
+    uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return __uint_as_float(b);
+}
+
+__device__ __forceinline__ bool finite_f(float v) {
+    return (__float_as_uint(v) & 0x7F800000u) != 0x7F800000u;
+}
+
+struct Proj {
+    int status;
+    int i0, i1, j0, j1;
+    float ur, vr, r2;
+    double zc, sig;
+};
+
+__device__ Proj project_spec(const CamDev &c, float x, float y, float z, float h, double soh,
+                             double f) {
+#pragma clang fp contract(off)
+    Proj p;
+    p.i0 = p.i1 = p.j0 = p.j1 = 0;
+    p.ur = p.vr = p.r2 = 0.0f;
+    p.sig = 0.0;
+    double d0 = (double)x - c.eye[0];
+    double d1 = (double)y - c.eye[1];
+    double d2 = (double)z - c.eye[2];
+    double xc = (d0 * c.right[0] + d1 * c.right[1]) + d2 * c.right[2];
+    double yc = (d0 * c.up[0] + d1 * c.up[1]) + d2 * c.up[2];
+    double zc = (d0 * c.fwd[0] + d1 * c.fwd[1]) + d2 * c.fwd[2];
+    p.zc = zc;
+    if (!(zc > c.znear && zc <= c.zfar)) {
+        p.status = kDepthCulled;
+        return p;
+    }
+    double s = c.persp ? c.focal / zc : c.ppu;
+    double u = xc * s + c.half_w;
+    double v = yc * s + c.half_h;
+    double sig = ((double)h * soh) * s;
+    double r = f * sig;
+    p.sig = sig;
+    double a = (u - r) - 0.5, b = (u + r) - 0.5;
+    double cc = (v - r) - 0.5, dd = (v + r) - 0.5;
+    if (!(a <= b) || !(cc <= dd)) {
+        p.status = kOffscreen;
+        return p;
+    }
+    double i0 = ceil(a), i1 = floor(b), j0 = ceil(cc), j1 = floor(dd);
+    if (i0 < 0.0) i0 = 0.0;
+    if (i1 > c.wmax) i1 = c.wmax;
+    if (j0 < 0.0) j0 = 0.0;
+    if (j1 > c.hmax) j1 = c.hmax;
+    if (!(i0 <= i1) || !(j0 <= j1)) {
+        p.status = kOffscreen;
+        return p;
+    }
+    p.i0 = (int)i0;
+    p.i1 = (int)i1;
+    p.j0 = (int)j0;
+    p.j1 = (int)j1;
+    p.ur = (float)(u - i0);
+    p.vr = (float)(v - j0);
+    p.r2 = (float)(r * r);
+    p.status = kVisible;
+    return p;
+}
+
+__device__ __forceinline__ bool particle_valid(float x, float y, float z, float h, float v,
+                                               float r0, int sp, int ns) {
+    return finite_f(x) && finite_f(y) && finite_f(z) && finite_f(h) && finite_f(v) &&
+           h > 0.0f && sp < ns && finite_f(r0) && r0 >= 0.0f;
+}
+
+// Normalised scalar t in [0, 1] (binary32).
+__device__ __forceinline__ float normalise(float v, float vmin, float vmax, int log_scale) {
+    float gv, g0, g1;
+    if (log_scale) {
+        if (!(v > 0.0f) || !(vmin > 0.0f) || !(vmax > 0.0f)) return 0.0f;
+        gv = log10f(v);
+        g0 = log10f(vmin);
+        g1 = log10f(vmax);
+    } else {
+        gv = v;
+        g0 = vmin;
+        g1 = vmax;
+    }
+    float den = g1 - g0;
+    if (!(den > 0.0f)) return 0.0f;
+    float t = (gv - g0) / den;
+    return fminf(fmaxf(t, 0.0f), 1.0f);
+}
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
+}
+
+__global__ void k_fill_f32(float *p, float v, size_t n) {
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
+}
+
+// Min slots start at all-ones, max slots at zero.
+__global__ void k_init_range(uint32_t *range_bits) {
+    int t = threadIdx.x;
+    if (t < 2 * kMaxSpecies) range_bits[t] = (t & 1) ? 0u : 0xFFFFFFFFu;
+}
+
+// Exact per-species min/max of valid values (order-free: min and max of
+// binary32 values through their monotone unsigned images).
+__global__ __launch_bounds__(kThreads) void k_value_range(ProjectArgs a, uint32_t *range_bits) {
+    __shared__ uint32_t s_lo[kMaxSpecies], s_hi[kMaxSpecies];
+    const int ns = a.sp.n;
+    if (threadIdx.x < kMaxSpecies) {
+        s_lo[threadIdx.x] = 0xFFFFFFFFu;
+        s_hi[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    uint32_t lo[kMaxSpecies], hi[kMaxSpecies];
+#pragma unroll
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        lo[s] = 0xFFFFFFFFu;
+        hi[s] = 0u;
+    }
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < (size_t)a.n; k += stride) {
+        int sp = a.species ? (int)a.species[k] : 0;
+        float v = a.value[k];
+        float r0 = a.rho0 ? a.rho0[k] : 1.0f;
+        if (!particle_valid(a.x[k], a.y[k], a.z[k], a.h[k], v, r0, sp, ns)) continue;
+        if (!a.sp.auto_range[sp]) continue;
+        if (a.sp.log_scale[sp] && !(v > 0.0f)) continue;
+        uint32_t ob = order_bits(v);
+#pragma unroll
+        for (int s = 0; s < kMaxSpecies; ++s)
+            if (s == sp) {
+                lo[s] = min(lo[s], ob);
+                hi[s] = max(hi[s], ob);
+            }
+    }
+    for (int s = 0; s < ns; ++s) {
+        uint32_t l = lo[s], h = hi[s];
+        for (int o = 32; o > 0; o >>= 1) {
+            l = min(l, (uint32_t)__shfl_xor((int)l, o, 64));
+            h = max(h, (uint32_t)__shfl_xor((int)h, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0 && l != 0xFFFFFFFFu) {
+            atomicMin(&s_lo[s], l);
+            atomicMax(&s_hi[s], h);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < ns && s_lo[threadIdx.x] != 0xFFFFFFFFu) {
+        atomicMin(&range_bits[2 * threadIdx.x], s_lo[threadIdx.x]);
+        atomicMax(&range_bits[2 * threadIdx.x + 1], s_hi[threadIdx.x]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
+    __shared__ unsigned s_cnt[kCntN];
+    if (threadIdx.x < kCntN) s_cnt[threadIdx.x] = 0;
+    __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
+    if (threadIdx.x < kMaxSpecies) {
+        int s = threadIdx.x;
+        float lo = a.sp.vmin[s], hi = a.sp.vmax[s];
+        if (s < a.sp.n && a.sp.auto_range[s] && a.range_bits) {
+            uint32_t bl = a.range_bits[2 * s], bh = a.range_bits[2 * s + 1];
+            if (bl == 0xFFFFFFFFu) {
+                lo = hi = 0.0f;  // no valid value in this species
+            } else {
+                lo = from_order_bits(bl);
+                hi = from_order_bits(bh);
+            }
+        }
+        s_vmin[s] = lo;
+        s_vmax[s] = hi;
+    }
+    __syncthreads();
+    unsigned my[kCntN] = {0, 0, 0, 0};
+    const int T = a.tile;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < (size_t)a.n; k += stride) {
+        float x = a.x[k], y = a.y[k], z = a.z[k], h = a.h[k], v = a.value[k];
+        int sp = a.species ? (int)a.species[k] : 0;
+        float r0 = a.rho0 ? a.rho0[k] : 1.0f;
+        Proj p;
+        if (!particle_valid(x, y, z, h, v, r0, sp, a.sp.n)) {
+            p.status = kInvalid;
+            p.i0 = p.i1 = p.j0 = p.j1 = 0;
+            p.ur = p.vr = p.r2 = 0.0f;
+            p.zc = 0.0;
+            p.sig = 0.0;
+        } else {
+            p = project_spec(a.cam, x, y, z, h, a.soh, a.f);
+        }
+        uint32_t cnt = 0, key = kEmptyKey;
+        if (p.status == kVisible) {
+            float t = normalise(v, s_vmin[sp], s_vmax[sp], a.sp.log_scale[sp]);
+            double qs = 1.4426950408889634 / (p.sig * p.sig);
+            float qsf = (float)fmin(qs, (double)FLT_MAX);
+            Rec r;
+            r.a.x = (uint32_t)p.i0 | ((uint32_t)p.i1 << kBboxBits) | ((uint32_t)sp << 28);
+            r.a.y = (uint32_t)p.j0 | ((uint32_t)p.j1 << kBboxBits);
+            r.a.z = __float_as_uint(p.ur);
+            r.a.w = __float_as_uint(p.vr);
+            r.b.x = __float_as_uint(p.r2);
+            r.b.y = __float_as_uint(qsf);
+            r.b.z = __float_as_uint(t);
+            r.b.w = __float_as_uint(r0);
+            a.rec[k] = r;
+            cnt = (uint32_t)((p.i1 / T - p.i0 / T + 1) * (p.j1 / T - p.j0 / T + 1));
+            key = order_bits((float)p.zc);
+        }
+        a.cnt[k] = cnt;
+        if (a.key) a.key[k] = key;
+        if (a.o_status) a.o_status[k] = (int8_t)p.status;
+        if (a.o_bbox) {
+            int4 bb = make_int4(p.i0, p.i1, p.j0, p.j1);
+            reinterpret_cast<int4 *>(a.o_bbox)[k] = bb;
+        }
+        if (a.o_spec) {
+            a.o_spec[3 * k + 0] = p.ur;
+            a.o_spec[3 * k + 1] = p.vr;
+            a.o_spec[3 * k + 2] = p.r2;
+        }
+        if (a.o_key) a.o_key[k] = p.status == kVisible ? key : 0u;
+        my[p.status] += 1;
+    }
+#pragma unroll
+    for (int c = 0; c < kCntN; ++c) {
+        unsigned w = wave_sum(my[c]);
+        if ((threadIdx.x & 63) == 0 && w) atomicAdd(&s_cnt[c], w);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCntN && s_cnt[threadIdx.x])
+        atomicAdd(&a.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+}
+
+unsigned grid_for(size_t n, unsigned cap) {
+    size_t g = (n + kThreads - 1) / kThreads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 65536)), dim3(kThreads), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 65536)), dim3(kThreads), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_value_range(const ProjectArgs &a, uint32_t *range_bits, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_range, dim3(1), dim3(2 * kMaxSpecies), 0, s, range_bits);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.n == 0) return e;
+    hipLaunchKernelGGL(k_value_range, dim3(grid_for((size_t)a.n, 4096)), dim3(kThreads), 0, s,
+                       a, range_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const ProjectArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3(grid_for((size_t)a.n, 1u << 20)), dim3(kThreads), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+}  // namespace splotch

@@ -1,0 +1,304 @@
+// Device-wide exclusive scans and a stable LSD radix sort of (key, value)
+// pairs, written for wave64: 256-thread workgroups, 4096 keys per
+// workgroup tile, 8-bit digits.
+//
+// Each radix pass is reduce-then-scan: a histogram kernel counts digits per
+// tile (digit-major, so one exclusive scan yields every tile's output
+// offset per digit), then the scatter kernel ranks keys inside the tile
+// (wave ballots find equal digits, lanes in order, waves in order: stable),
+// reorders the tile in LDS and writes each digit run contiguously.
+#include "internal.h"
+
+namespace splotch {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kW = kT / 64;
+constexpr int kIpt = 16;
+constexpr int kTile = kT * kIpt;  // 4096
+
+__device__ __forceinline__ uint32_t shfl_up_u32(uint32_t v, int o) {
+    return (uint32_t)__shfl_up((int)v, o, 64);
+}
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int o) {
+    uint32_t lo = shfl_up_u32((uint32_t)v, o), hi = shfl_up_u32((uint32_t)(v >> 32), o);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t shfl_up_t(uint32_t v, int o) { return shfl_up_u32(v, o); }
+__device__ __forceinline__ uint64_t shfl_up_t(uint64_t v, int o) { return shfl_up_u64(v, o); }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T t = shfl_up_t(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan across the workgroup (NW waves); s_w has NW slots.
+template <int NW, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *s_w, T *total) {
+    T inc = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        T x = s_w[k];
+        if (k < w) pre += x;
+        tot += x;
+    }
+    *total = tot;
+    __syncthreads();
+    return pre + inc - v;
+}
+
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kT) void k_scan_reduce(const TI *in, size_t n, TO *partial) {
+    __shared__ TO s_w[kW];
+    const size_t base = (size_t)blockIdx.x * kTile;
+    TO s = 0;
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        size_t idx = base + (size_t)q * kT + threadIdx.x;
+        if (idx < n) s += (TO)in[idx];
+    }
+    TO tot;
+    block_excl_scan<kW>(s, s_w, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+template <typename TO>
+__global__ __launch_bounds__(1024) void k_scan_partials(TO *partial, size_t m, TO *total_out) {
+    __shared__ TO s_w[16];
+    TO carry = 0;
+    for (size_t base = 0; base < m; base += 1024) {
+        size_t idx = base + threadIdx.x;
+        TO v = idx < m ? partial[idx] : (TO)0;
+        TO tot;
+        TO ex = block_excl_scan<16>(v, s_w, &tot);
+        if (idx < m) partial[idx] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kT) void k_scan_down(const TI *in, TO *out, size_t n,
+                                                  const TO *partial) {
+    __shared__ TO s[kTile + kTile / 16];
+    __shared__ TO s_w[kW];
+    const size_t base = (size_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        int l = q * kT + threadIdx.x;
+        size_t idx = base + l;
+        s[pad(l)] = idx < n ? (TO)in[idx] : (TO)0;
+    }
+    __syncthreads();
+    TO v[kIpt];
+    TO sum = 0;
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+        v[i] = s[pad(threadIdx.x * kIpt + i)];
+        sum += v[i];
+    }
+    TO tot;
+    TO run = partial[blockIdx.x] + block_excl_scan<kW>(sum, s_w, &tot);
+#pragma unroll
+    for (int i = 0; i < kIpt; ++i) {
+        s[pad(threadIdx.x * kIpt + i)] = run;
+        run += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        int l = q * kT + threadIdx.x;
+        size_t idx = base + l;
+        if (idx < n) out[idx] = s[pad(l)];
+    }
+}
+
+template <typename TO>
+__global__ void k_set_value(TO *p, TO v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+template <typename TI, typename TO>
+hipError_t scan_impl(const TI *in, TO *out, size_t n, TO *total_out, void *scratch,
+                     hipStream_t s) {
+    if (n == 0) {
+        if (total_out) hipLaunchKernelGGL(k_set_value<TO>, dim3(1), dim3(64), 0, s, total_out, (TO)0);
+        return hipGetLastError();
+    }
+    size_t nb = (n + kTile - 1) / kTile;
+    TO *partial = reinterpret_cast<TO *>(scratch);
+    hipLaunchKernelGGL((k_scan_reduce<TI, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, n,
+                       partial);
+    hipLaunchKernelGGL(k_scan_partials<TO>, dim3(1), dim3(1024), 0, s, partial, nb, total_out);
+    hipLaunchKernelGGL((k_scan_down<TI, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, out, n,
+                       partial);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n, int shift,
+                                                uint32_t *hist, uint32_t nblocks) {
+    __shared__ uint32_t sh[kW][256];
+    for (int d = threadIdx.x; d < kW * 256; d += kT) (&sh[0][0])[d] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const size_t base = (size_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        size_t idx = base + (size_t)q * kT + threadIdx.x;
+        if (idx < n) atomicAdd(&sh[w][(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) t += sh[k][threadIdx.x];
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
+                                                   uint32_t *kout, uint32_t *vout, size_t n,
+                                                   int shift, const uint32_t *hist,
+                                                   uint32_t nblocks, int write_keys) {
+    __shared__ uint32_t s_k[kTile], s_v[kTile];
+    __shared__ uint32_t s_wc[kW][256];
+    __shared__ uint32_t s_bs[256], s_go[256], s_sw[kW];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const size_t base = (size_t)blockIdx.x * kTile;
+    for (int d = tid; d < kW * 256; d += kT) (&s_wc[0][0])[d] = 0;
+    uint32_t k[kIpt], v[kIpt], r[kIpt];
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        size_t idx = base + (size_t)w * (kIpt * 64) + (size_t)j * 64 + lane;
+        if (idx < n) {
+            k[j] = kin[idx];
+            v[j] = vin ? vin[idx] : (uint32_t)idx;
+        } else {
+            k[j] = 0xFFFFFFFFu;
+            v[j] = 0u;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t d = (k[j] >> shift) & 255u;
+        uint64_t m = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & lt);
+        const uint32_t c = s_wc[w][d];
+        r[j] = c + rank;
+        if (rank == 0) s_wc[w][d] = c + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t wpre[kW];
+    uint32_t dtot = 0;
+#pragma unroll
+    for (int ww = 0; ww < kW; ++ww) {
+        wpre[ww] = dtot;
+        dtot += s_wc[ww][tid];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kW>(dtot, s_sw, &tot);
+    s_bs[tid] = ex;
+#pragma unroll
+    for (int ww = 0; ww < kW; ++ww) s_wc[ww][tid] = wpre[ww];
+    s_go[tid] = hist[(size_t)tid * nblocks + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t d = (k[j] >> shift) & 255u;
+        const uint32_t pos = s_bs[d] + s_wc[w][d] + r[j];
+        s_k[pos] = k[j];
+        s_v[pos] = v[j];
+    }
+    __syncthreads();
+    const size_t rem = n - base;
+    const int nvalid = rem < (size_t)kTile ? (int)rem : kTile;
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        int p = q * kT + tid;
+        if (p < nvalid) {
+            uint32_t key = s_k[p];
+            uint32_t d = (key >> shift) & 255u;
+            size_t g = (size_t)s_go[d] + (size_t)(p - (int)s_bs[d]);
+            if (write_keys) kout[g] = key;
+            vout[g] = s_v[p];
+        }
+    }
+}
+
+}  // namespace
+
+size_t scan_u32_u64_scratch_bytes(size_t n) {
+    return align_up(((n + kTile - 1) / kTile + 1) * sizeof(uint64_t), 256);
+}
+
+hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void *scratch,
+                               hipStream_t s) {
+    return scan_impl<uint32_t, uint64_t>(in, out, n, out + n, scratch, s);
+}
+
+size_t scan_u32_scratch_bytes(size_t n) {
+    return align_up(((n + kTile - 1) / kTile + 1) * sizeof(uint32_t), 256);
+}
+
+hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t s) {
+    return scan_impl<uint32_t, uint32_t>(data, data, n, nullptr, scratch, s);
+}
+
+size_t radix_scratch_bytes(size_t n) {
+    size_t nb = (n + kTile - 1) / kTile;
+    if (nb == 0) nb = 1;
+    size_t hist = align_up(nb * 256 * sizeof(uint32_t), 256);
+    return hist + scan_u32_scratch_bytes(nb * 256);
+}
+
+hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
+                            bool vals_identity, size_t n, int bits, bool keys_needed,
+                            void *scratch, bool *result_in_1, hipStream_t s) {
+    *result_in_1 = false;
+    if (n == 0) return hipSuccess;
+    const uint32_t nb = (uint32_t)((n + kTile - 1) / kTile);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(scratch);
+    void *scan_scratch =
+        reinterpret_cast<char *>(scratch) + align_up((size_t)nb * 256 * sizeof(uint32_t), 256);
+    const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+    int src = 0;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
+        uint32_t *kout = src ? k0 : k1, *vout = src ? v0 : v1;
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kT), 0, s, kin, n, shift, hist, nb);
+        hipError_t e = launch_scan_u32(hist, (size_t)nb * 256, scan_scratch, s);
+        if (e != hipSuccess) return e;
+        const bool last = p == passes - 1;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kT), 0, s, kin,
+                           (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin, kout,
+                           vout, n, shift, hist, nb, (!last || keys_needed) ? 1 : 0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        src ^= 1;
+    }
+    *result_in_1 = src == 1;
+    return hipSuccess;
+}
+
+}  // namespace splotch

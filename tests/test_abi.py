@@ -1,0 +1,163 @@
+"""Host-side checks of the C ABI: no GPU needed, no compute launched.
+
+Every argument error below is detected on the host before any HIP call,
+so these run on a machine without a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1004_1302_amd import binding as B
+from paper_1004_1302_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "splotch.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(splotch_\w+)\s*\(", txt, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    lib = B.lib()
+    names = declared_functions()
+    assert len(names) >= 6
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_status_strings():
+    for code in range(6):
+        s = B.status_string(code)
+        assert isinstance(s, str) and s
+    assert B.status_string(0) == "ok"
+    assert B.status_string(99) == "unknown status"
+
+
+def _params(**kw):
+    return B.params_struct([synth.Species()], **kw)
+
+
+def test_camera_look_at_frame():
+    c = B.camera_look_at((1, 2, 3), (4, -2, 9), (0, 1, 0), B.PERSPECTIVE, 60.0, 640, 480, 0.1, 100)
+    R, U, F = (np.array(list(getattr(c, k)), np.float64) for k in ("right", "up", "fwd"))
+    assert np.allclose([R @ R, U @ U, F @ F], 1, atol=1e-6)
+    assert np.allclose([R @ U, R @ F, U @ F], 0, atol=1e-6)
+    assert np.allclose(np.cross(R, U), F, atol=1e-6)
+    assert c.focal_px == pytest.approx(320 / np.tan(np.radians(30)), rel=1e-6)
+    # agrees with the generator's frame construction
+    g = synth.look_at((1, 2, 3), (4, -2, 9), (0, 1, 0), B.PERSPECTIVE, 640, 480, 60.0)
+    assert np.allclose(R, g.right, atol=1e-6) and np.allclose(U, g.up, atol=1e-6)
+    with pytest.raises(B.SplotchError):
+        B.camera_look_at((0, 0, 0), (0, 0, 0), (0, 1, 0), B.PERSPECTIVE, 60.0, 64, 64, 0.1, 10)
+    with pytest.raises(B.SplotchError):
+        B.camera_look_at((0, 0, 0), (0, 1, 0), (0, 1, 0), B.PERSPECTIVE, 60.0, 64, 64, 0.1, 10)
+
+
+def _ws_size(n, cam, prm, pairs=0):
+    out = C.c_size_t()
+    code = B.lib().splotch_workspace_size(n, C.byref(cam), C.byref(prm), pairs, C.byref(out))
+    return code, out.value
+
+
+def test_workspace_size_monotone():
+    cam = B.camera_struct(synth.ortho_unit_square(256, 256))
+    prm = _params()
+    sizes = [_ws_size(n, cam, prm)[1] for n in (0, 1, 1000, 10 ** 5, 10 ** 7)]
+    assert all(b > a for a, b in zip(sizes, sizes[1:]))
+    assert _ws_size(1000, cam, prm, 10 ** 6)[1] > _ws_size(1000, cam, prm, 10 ** 4)[1]
+    # an ordered species needs the depth-sort buffers
+    prm_o = B.params_struct([synth.Species(mode=synth.ORDERED, absorption=1.0)])
+    assert _ws_size(10 ** 5, cam, prm_o)[1] > _ws_size(10 ** 5, cam, prm)[1]
+    assert _ws_size(-1, cam, prm)[0] == 1
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("width", 0, 1), ("height", -3, 1), ("width", 20000, 1), ("projection", 7, 1),
+    ("px_per_unit", 0.0, 1), ("z_far", -5.0, 1),
+])
+def test_camera_validation(field, value, code):
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    setattr(cam, field, value)
+    assert _ws_size(10, cam, _params())[0] == code
+
+
+def test_non_orthonormal_frame_rejected():
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    cam.up[:] = [0.0, 1.0, 0.1]
+    assert _ws_size(10, cam, _params())[0] == 1
+
+
+def test_perspective_needs_positive_near_and_focal():
+    cam = B.camera_struct(synth.look_at((0, 0, -5), (0, 0, 0), (0, 1, 0), B.PERSPECTIVE, 64, 64))
+    assert _ws_size(10, cam, _params())[0] == 0
+    cam.z_near = 0.0
+    assert _ws_size(10, cam, _params())[0] == 1
+    cam.z_near = 0.1
+    cam.focal_px = -1.0
+    assert _ws_size(10, cam, _params())[0] == 1
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(sigma_over_h=0.0), 1), (dict(trunc_f=-1.0), 1), (dict(tile=12), 4), (dict(tile=64), 4),
+])
+def test_param_validation(kw, code):
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    assert _ws_size(10, cam, _params(**kw))[0] == code
+
+
+def test_species_validation():
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    bad = [synth.Species(mode=5), synth.Species(absorption=-1.0),
+           synth.Species(vmin=-1.0, vmax=2.0, log_scale=1)]
+    for s in bad:
+        assert _ws_size(10, cam, B.params_struct([s]))[0] == 1
+    p = B.params_struct([synth.Species()])
+    p.n_species = 0
+    assert _ws_size(10, cam, p)[0] == 1
+    p.n_species = 9
+    assert _ws_size(10, cam, p)[0] == 1
+
+
+def test_render_rejects_before_launch():
+    """Argument errors come back before any device work (no GPU here)."""
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    prm = _params()
+    P = B.Particles()
+    P.n = 10  # null pointers with n > 0
+    cm = B.Colourmap(256, C.c_void_p(0x1000))
+    img = B.Image(C.c_void_p(0x2000), 64, 64)
+    lib = B.lib()
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(img)) == 1
+    P.n = 0
+    # no workspace
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(img)) == 2
+    # misaligned workspace
+    prm.workspace = C.c_void_p(0x1001)
+    prm.workspace_bytes = 1 << 30
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(img)) == 2
+    # too small
+    prm.workspace = C.c_void_p(0x100000)
+    prm.workspace_bytes = 100
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(img)) == 2
+    prm.workspace_bytes = 1 << 30
+    # palette with one entry, image of the wrong size
+    bad_cm = B.Colourmap(1, C.c_void_p(0x1000))
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(bad_cm), C.byref(prm), C.byref(img)) == 1
+    bad_img = B.Image(C.c_void_p(0x2000), 32, 64)
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(bad_img)) == 1
+    P.n = 1 << 32
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(img)) == 1
+
+
+def test_bin_and_project_validate():
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    prm = _params(tile=24)
+    P = B.Particles()
+    lib = B.lib()
+    assert lib.splotch_project(C.byref(P), C.byref(cam), C.byref(prm), None, None, None, None, None) == 4
+    n = C.c_int64()
+    assert lib.splotch_bin(C.byref(P), C.byref(cam), C.byref(prm), None, None, None, 0, C.byref(n)) == 4
