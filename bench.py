@@ -77,7 +77,8 @@ def cpu_baseline(parts, cam, sp, args, np, torch):
     k = min(n, int(args.cpu_sample))
     gen = torch.Generator(device="cpu")
     gen.manual_seed(17)
-    idx = torch.randperm(n, generator=gen)[:k].sort().values.to(parts["x"].device)
+    idx = torch.unique(torch.randint(0, n, (k,), generator=gen)).to(parts["x"].device)
+    k = int(idx.numel())
     host = {key: t[idx].cpu().numpy() for key, t in parts.items()}
     scene = synth.Scene(host["x"], host["y"], host["z"], host["h"], host["value"], cam, sp,
                         species=host.get("species"), rho0=host.get("rho0"))

@@ -148,6 +148,9 @@ typedef struct splotch_params {
     int32_t compensated; /* 1: compensated (Kahan) summation of emission */
     int32_t tile;        /* tile edge in pixels: 0 (= 16), 8, 16 or 32 */
     int32_t profile;     /* 1: time each stage (needs stats) */
+    int32_t seg_records; /* least records per tile-list segment (one workgroup
+                            each); 0 = 1024.  Long lists are cut into segments
+                            merged front to back; this only affects speed. */
     void *stream;        /* hipStream_t */
     void *workspace;     /* device, >= splotch_workspace_size() bytes, 256-aligned */
     size_t workspace_bytes;
@@ -215,6 +218,32 @@ splotch_status splotch_bin(const splotch_particles *particles, const splotch_cam
                            const splotch_params *params, uint32_t *tile_start,
                            uint32_t *tile_end, uint32_t *pair_particle, int64_t max_out,
                            int64_t *n_pairs);
+
+/* Render n_views camera views (1..SPLOTCH_MAX_VIEWS, sizes may differ) of
+ * one particle set with shared colour settings into images[v] (Section 3.2
+ * stages per view).  Nothing is read back between stages: every size is
+ * kept on the device, so the whole batch is one stream-ordered sequence.
+ * With use_graph = 1 the sequence is captured into a HIP graph on the first
+ * call and replayed by later calls whose arguments (all pointers, sizes and
+ * settings) are identical; params->stream must then be a created stream
+ * (not the null stream).  The workspace is sized with
+ * splotch_workspace_size for the view with the most tiles; views are
+ * rendered one after another through it.  There is no chunking: a view
+ * whose pairs exceed the workspace's pair capacity is left incomplete and
+ * flagged.  If params->stats is not NULL it must point to n_views structs;
+ * the call then waits for the batch, fills n_pairs (and tile, ordered) per
+ * view, and returns SPLOTCH_E_CAPACITY if any view overflowed (its
+ * n_chunks is then 0).  Without stats the call returns as soon as the work
+ * is queued. */
+#define SPLOTCH_MAX_VIEWS 1024
+splotch_status splotch_render_batch(const splotch_particles *particles, int32_t n_views,
+                                    const splotch_camera *cams, const splotch_colourmap *cmap,
+                                    const splotch_params *params, splotch_image *images,
+                                    int32_t use_graph);
+
+/* Destroy every cached HIP graph (see splotch_render_batch).  Returns the
+ * number destroyed. */
+int32_t splotch_graph_cache_clear(void);
 
 #ifdef __cplusplus
 }

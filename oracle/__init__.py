@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -170,7 +170,9 @@ def render(scene, img_in=None) -> np.ndarray:
 
 
 def render_pixels(scene, pi, pj, in_px=None) -> np.ndarray:
-    """FP64 values (npx, 3) at the sample pixels (pi[k], pj[k])."""
+    """FP64 values (npx, 3) at the sample pixels (pi[k], pj[k]).  The scan
+    over particles runs on all OpenMP threads; the composite is the same
+    for any thread count."""
     x, y, z, h, v, r0, sp = _parts(scene)
     s = _species_arrays(scene.species_params)
     cam = scene.camera

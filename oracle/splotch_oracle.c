@@ -42,6 +42,9 @@
  * GPU implementation may call it; only tests and the CPU-baseline timing do.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -421,43 +424,78 @@ int64_t orc_render_pixels(int64_t n, const float *x, const float *y, const float
     int64_t *fill = (int64_t *)calloc((size_t)H, sizeof(int64_t));
     for (int64_t s = 0; s < npx; ++s) order[row_first[pj[s]] + fill[pj[s]]++] = s;
     free(fill);
-    size_t cap = 1024, nh = 0;
-    hit_t *hits = (hit_t *)malloc(sizeof(hit_t) * cap);
-    for (int64_t k = 0; k < n; ++k) {
-        if (!particle_valid(k, x, y, z, h, value, rho0, species, ns)) continue;
-        proj_t p = project_one(&c, x[k], y[k], z[k], h[k], (double)sigma_over_h,
-                               (double)trunc_f);
-        if (p.status != ORC_VISIBLE) continue;
-        int s = species ? species[k] : 0;
-        int colour_done = 0;
-        double col[3];
-        for (int j = p.j0; j <= p.j1; ++j)
-            for (int64_t q = row_first[j]; q < row_first[j + 1]; ++q) {
-                int64_t smp = order[q];
-                if (!member32(&p, pi[smp], j)) continue;
-                if (!colour_done) {
-                    double t = orc_normalise(value[k], lo[s], hi[s], log_scale[s]);
-                    orc_palette(t, K, pal, col);
-                    colour_done = 1;
+    /* The particle scan is split over threads; each keeps its own hit list.
+     * The lists are concatenated and put in the total order
+     * (sample, depth key, index), so the result does not depend on the
+     * number of threads. */
+    int nthr = 1;
+#ifdef _OPENMP
+    nthr = omp_get_max_threads();
+#endif
+    hit_t **tl = (hit_t **)calloc((size_t)nthr, sizeof(hit_t *));
+    size_t *tn = (size_t *)calloc((size_t)nthr, sizeof(size_t));
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthr)
+#endif
+    {
+        int me = 0;
+#ifdef _OPENMP
+        me = omp_get_thread_num();
+#endif
+        size_t cap = 1024, nh = 0;
+        hit_t *hits = (hit_t *)malloc(sizeof(hit_t) * cap);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (int64_t k = 0; k < n; ++k) {
+            if (!particle_valid(k, x, y, z, h, value, rho0, species, ns)) continue;
+            proj_t p = project_one(&c, x[k], y[k], z[k], h[k], (double)sigma_over_h,
+                                   (double)trunc_f);
+            if (p.status != ORC_VISIBLE) continue;
+            int s = species ? species[k] : 0;
+            int colour_done = 0;
+            double col[3];
+            for (int j = p.j0; j <= p.j1; ++j)
+                for (int64_t q = row_first[j]; q < row_first[j + 1]; ++q) {
+                    int64_t smp = order[q];
+                    if (!member32(&p, pi[smp], j)) continue;
+                    if (!colour_done) {
+                        double t = orc_normalise(value[k], lo[s], hi[s], log_scale[s]);
+                        orc_palette(t, K, pal, col);
+                        colour_done = 1;
+                    }
+                    if (nh == cap) {
+                        cap *= 2;
+                        hits = (hit_t *)realloc(hits, sizeof(hit_t) * cap);
+                    }
+                    hit_t *e = &hits[nh++];
+                    e->key = p.key;
+                    e->idx = k;
+                    e->sample = (int32_t)smp;
+                    double dx = ((double)pi[smp] + 0.5) - p.u;
+                    double dy = ((double)j + 0.5) - p.v;
+                    double q2 = (dx * dx + dy * dy) / (p.sig * p.sig);
+                    e->contrib_tau = (rho0 ? (double)rho0[k] : 1.0) * exp(-q2);
+                    for (int ch = 0; ch < 3; ++ch) {
+                        e->E[ch] = (double)bright[s] * col[ch];
+                        e->A[ch] = mode[s] == 1 ? (double)absorb[s] * col[ch] : 0.0;
+                    }
                 }
-                if (nh == cap) {
-                    cap *= 2;
-                    hits = (hit_t *)realloc(hits, sizeof(hit_t) * cap);
-                }
-                hit_t *e = &hits[nh++];
-                e->key = p.key;
-                e->idx = k;
-                e->sample = (int32_t)smp;
-                double dx = ((double)pi[smp] + 0.5) - p.u;
-                double dy = ((double)j + 0.5) - p.v;
-                double q2 = (dx * dx + dy * dy) / (p.sig * p.sig);
-                e->contrib_tau = (rho0 ? (double)rho0[k] : 1.0) * exp(-q2);
-                for (int ch = 0; ch < 3; ++ch) {
-                    e->E[ch] = (double)bright[s] * col[ch];
-                    e->A[ch] = mode[s] == 1 ? (double)absorb[s] * col[ch] : 0.0;
-                }
-            }
+        }
+        tl[me] = hits;
+        tn[me] = nh;
     }
+    size_t nh = 0;
+    for (int t = 0; t < nthr; ++t) nh += tn[t];
+    hit_t *hits = (hit_t *)malloc(sizeof(hit_t) * (nh > 0 ? nh : 1));
+    size_t at = 0;
+    for (int t = 0; t < nthr; ++t) {
+        if (tn[t]) memcpy(hits + at, tl[t], tn[t] * sizeof(hit_t));
+        at += tn[t];
+        free(tl[t]);
+    }
+    free(tl);
+    free(tn);
     qsort(hits, nh, sizeof(hit_t), cmp_hit);
     for (int64_t s = 0; s < npx; ++s)
         for (int ch = 0; ch < 3; ++ch) out_px[3 * s + ch] = in_px ? in_px[3 * s + ch] : 0.0;

@@ -74,7 +74,8 @@ class Params(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("species", SpeciesS * MAX_SPECIES),
                 ("sigma_over_h", C.c_float), ("trunc_f", C.c_float),
                 ("accumulate", C.c_int32), ("compensated", C.c_int32), ("tile", C.c_int32),
-                ("profile", C.c_int32), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("profile", C.c_int32), ("seg_records", C.c_int32),
+                ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats))]
 
 
@@ -85,7 +86,9 @@ class Image(C.Structure):
 _L = None
 
 EXPORTS = ("splotch_status_string", "splotch_camera_look_at", "splotch_workspace_size",
-           "splotch_render", "splotch_project", "splotch_bin")
+           "splotch_render", "splotch_project", "splotch_bin", "splotch_render_batch",
+           "splotch_graph_cache_clear")
+MAX_VIEWS = 1024
 
 
 def _lib():
@@ -111,6 +114,12 @@ def _lib():
         L.splotch_project.argtypes = [C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Params),
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p]
+        L.splotch_render_batch.restype = C.c_int
+        L.splotch_render_batch.argtypes = [C.POINTER(Particles), C.c_int32, C.POINTER(CameraS),
+                                           C.POINTER(Colourmap), C.POINTER(Params),
+                                           C.POINTER(Image), C.c_int32]
+        L.splotch_graph_cache_clear.restype = C.c_int32
+        L.splotch_graph_cache_clear.argtypes = []
         L.splotch_bin.restype = C.c_int
         L.splotch_bin.argtypes = [C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Params),
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -159,7 +168,7 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 
 
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
-                  tile=0, profile=False) -> Params:
+                  tile=0, profile=False, seg_records=0) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
@@ -173,6 +182,7 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.compensated = 1 if compensated else 0
     p.tile = int(tile)
     p.profile = 1 if profile else 0
+    p.seg_records = int(seg_records)
     return p
 
 
@@ -253,14 +263,14 @@ def _setup(parts, cam, species, max_pairs, workspace, **kw):
 
 def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, trunc_f=2.0,
            accumulate=False, compensated=False, tile=0, max_pairs=0, workspace=None,
-           stats=False, profile=False):
+           stats=False, profile=False, seg_records=0):
     """Render into image (planar float32 [3, H, W] device tensor; allocated
     if None).  Returns the image, or (image, stats dict) with stats=True
     (profile=True adds per-stage milliseconds to the stats)."""
     import torch
     P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
                              trunc_f=trunc_f, accumulate=accumulate, compensated=compensated,
-                             tile=tile, profile=profile)
+                             tile=tile, profile=profile, seg_records=seg_records)
     stats = stats or profile
     if image is None:
         image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)
@@ -320,6 +330,77 @@ def bin_pairs(parts: dict, cam, species, *, sigma_over_h=1.0, trunc_f=2.0, tile=
     _check(_lib().splotch_bin(C.byref(P), C.byref(cs), C.byref(prm), _ptr(ts), _ptr(te),
                               _ptr(pp), int(cap), C.byref(npairs)), "splotch_bin")
     return ts, te, pp[: npairs.value], int(npairs.value)
+
+
+_streams: dict = {}
+
+
+def _side_stream(device):
+    """A created (non-null) stream per device for graph capture and replay."""
+    import torch
+    key = str(device)
+    if key not in _streams:
+        _streams[key] = torch.cuda.Stream(device=device)
+    return _streams[key]
+
+
+def render_batch(parts: dict, cams, palette, species, images=None, *, graph=False,
+                 sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False, tile=0,
+                 max_pairs=0, seg_records=0, workspace=None, stats=False):
+    """Render several camera views of one particle set (splotch_render_batch).
+    images: list of [3, H_v, W_v] float32 device tensors (allocated if None).
+    graph=True captures the batch into a HIP graph on first use and replays
+    it while every argument stays the same (same tensors, same settings).
+    Returns images, or (images, per-view stats) with stats=True."""
+    import torch
+    P = particles_struct(parts)
+    dev = parts["x"].device
+    nv = len(cams)
+    if not 1 <= nv <= MAX_VIEWS:
+        raise ValueError(f"1..{MAX_VIEWS} views")
+    cs = (CameraS * nv)(*[c if isinstance(c, CameraS) else camera_struct(c) for c in cams])
+    prm = params_struct(species, sigma_over_h=sigma_over_h, trunc_f=trunc_f,
+                        accumulate=accumulate, compensated=compensated, tile=tile,
+                        seg_records=seg_records)
+    T = tile or 16
+    big = max(range(nv), key=lambda v: (-(-cs[v].width // T)) * (-(-cs[v].height // T)))
+    if workspace is None:
+        need = workspace_bytes(P.n, cs[big], prm, max_pairs or 0)
+        workspace = get_workspace(need, dev)
+        nbytes = need
+    else:
+        nbytes = int(workspace.numel())
+    prm.workspace = C.c_void_p(workspace.data_ptr())
+    prm.workspace_bytes = nbytes
+    if images is None:
+        images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=dev) for c in cs]
+    for im, c in zip(images, cs):
+        if im.dtype != torch.float32 or not im.is_contiguous() or \
+                tuple(im.shape) != (3, c.height, c.width):
+            raise ValueError("each image must be contiguous float32 [3, H, W] of its camera")
+    ims = (Image * nv)(*[Image(C.c_void_p(im.data_ptr()), c.width, c.height)
+                         for im, c in zip(images, cs)])
+    cm = Colourmap(int(palette.shape[0]), C.c_void_p(palette.data_ptr()))
+    st = (Stats * nv)()
+    if stats:
+        prm.stats = C.cast(st, C.POINTER(Stats))
+    cur = torch.cuda.current_stream(dev)
+    if graph:
+        side = _side_stream(dev)
+        side.wait_stream(cur)
+        prm.stream = C.c_void_p(side.cuda_stream)
+    else:
+        prm.stream = C.c_void_p(cur.cuda_stream)
+    code = _lib().splotch_render_batch(C.byref(P), nv, cs, C.byref(cm), C.byref(prm), ims,
+                                       1 if graph else 0)
+    if graph:
+        cur.wait_stream(side)
+    _check(code, "splotch_render_batch")
+    return (images, [s.as_dict() for s in st]) if stats else images
+
+
+def graph_cache_clear() -> int:
+    return int(_lib().splotch_graph_cache_clear())
 
 
 @dataclass

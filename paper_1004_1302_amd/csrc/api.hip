@@ -5,6 +5,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <list>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "../../include/splotch.h"
@@ -16,10 +19,14 @@ namespace {
 
 constexpr uint32_t kMaxChunks = 4096;
 constexpr uint64_t kMaxPairCap = 0xFFFF0000ull;  // pair indices are 32-bit
+constexpr uint32_t kSegMin = 1024;               // least records per list segment
 
 struct Layout {
     size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
-    size_t tstart, tend, mcount, pk0, pk1, pv0, pv1;
+    size_t tstart, tend, mcount, seg_len, nseg, nmulti, seg_off, part_off, seg_scan, item_tile;
+    size_t partial, flags;
+    size_t pk0, pk1, pv0, pv1;
+    uint64_t max_items, max_slots;
     size_t total;
     uint64_t pair_cap;
     uint32_t n_tiles;
@@ -69,6 +76,19 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
     L.tstart = take((size_t)L.n_tiles * 4);
     L.tend = take((size_t)L.n_tiles * 4);
     L.mcount = take((size_t)L.n_tiles * 16);
+    // segments: seg_len >= max(1024, pairs / kSegTarget) keeps the number of
+    // items <= n_tiles + kSegTarget and partial slots < 2 * kSegTarget
+    L.max_items = (uint64_t)L.n_tiles + kSegTarget + 64;
+    L.max_slots = std::min<uint64_t>(2 * kSegTarget, 2 * (cap / 1024) + 2);
+    L.seg_len = take(4);
+    L.flags = take((size_t)SPLOTCH_MAX_VIEWS * 12);  // per view: overflow flag (u32), pairs (u64)
+    L.nseg = take((size_t)L.n_tiles * 4);
+    L.nmulti = take((size_t)L.n_tiles * 4);
+    L.seg_off = take(((size_t)L.n_tiles + 1) * 8);
+    L.part_off = take(((size_t)L.n_tiles + 1) * 8);
+    L.seg_scan = take(scan_u32_u64_scratch_bytes(L.n_tiles));
+    L.item_tile = take(L.max_items * 4);
+    L.partial = take(L.max_slots * 6 * (size_t)L.tile * L.tile * 4);
     L.pk0 = take(cap * 4);
     L.pk1 = take(cap * 4);
     L.pv0 = take(cap * 4);
@@ -134,6 +154,7 @@ splotch_status validate_params(const splotch_params *p) {
     if (p->tile != 0 && p->tile != 8 && p->tile != 16 && p->tile != 32)
         return SPLOTCH_E_UNSUPPORTED;
     if (p->accumulate != 0 && p->accumulate != 1) return SPLOTCH_E_INVALID_ARG;
+    if (p->seg_records < 0) return SPLOTCH_E_INVALID_ARG;
     for (int s = 0; s < p->n_species; ++s) {
         const splotch_species &q = p->species[s];
         if (q.mode != SPLOTCH_ADDITIVE && q.mode != SPLOTCH_ORDERED) return SPLOTCH_E_INVALID_ARG;
@@ -237,6 +258,7 @@ struct Ctx {
     Layout L;
     char *ws;
     hipStream_t s;
+    uint32_t seg_min = kSegMin;
     Prof prof;
     template <typename T>
     T *at(size_t off) const {
@@ -291,7 +313,7 @@ splotch_status run_order_and_scan(const Ctx &c, int64_t n, const uint32_t **orde
         bool in1 = false;
         uint32_t *k0 = c.at<uint32_t>(c.L.key0), *k1 = c.at<uint32_t>(c.L.key1);
         uint32_t *v0 = c.at<uint32_t>(c.L.val0), *v1 = c.at<uint32_t>(c.L.val1);
-        TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, 32, false,
+        TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, nullptr, 32, false,
                              c.at<void>(c.L.radix), &in1, c.s));
         const uint32_t *ord = in1 ? v1 : v0;
         // key buffers are free after the sort: counts in processing order
@@ -321,6 +343,8 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t
     e.first = first;
     e.last = last;
     e.base = off_first;
+    e.cap = c.L.pair_cap;
+    e.overflow = nullptr;
     e.tile = c.L.tile;
     e.ntx = c.L.ntx;
     e.pair_key = pk0;
@@ -330,11 +354,11 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t
     int bits = 0;
     while ((1ull << bits) < (uint64_t)c.L.n_tiles) ++bits;
     bool in1 = false;
-    TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)npairs, bits, true,
+    TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)npairs, nullptr, bits, true,
                          c.at<void>(c.L.radix), &in1, c.s));
     const uint32_t *keys = in1 ? pk1 : pk0;
     *vals = in1 ? pv1 : pv0;
-    TRY(launch_tile_ranges(keys, (size_t)npairs, c.at<uint32_t>(c.L.tstart),
+    TRY(launch_tile_ranges(keys, (size_t)npairs, nullptr, c.at<uint32_t>(c.L.tstart),
                            c.at<uint32_t>(c.L.tend), c.L.n_tiles, c.s));
     TRY(const_cast<Prof &>(c.prof).mark(4));
     return SPLOTCH_OK;
@@ -360,6 +384,19 @@ splotch_status plan_chunks(const Ctx &c, int64_t n, std::vector<uint64_t> *plan)
     if (hb[1] != 0) return SPLOTCH_E_CAPACITY;
     const uint64_t nch = hb[0];
     plan->assign(hb.begin() + 2, hb.begin() + 2 + 2 * (nch + 1));
+    return SPLOTCH_OK;
+}
+
+splotch_status run_splat_pass(Ctx &c, SplatArgs &sa, uint64_t npairs) {
+    const uint32_t nt = (uint32_t)(c.L.tile * c.L.tile);
+    const uint32_t seg_len = seg_len_rule(npairs, nt, c.seg_min);
+    TRY(launch_segments(sa.tile_start, sa.tile_end, c.L.n_tiles, npairs, nullptr, nt, c.seg_min,
+                        c.at<uint32_t>(c.L.seg_len), c.at<uint32_t>(c.L.nseg),
+                        c.at<uint32_t>(c.L.nmulti), c.at<uint64_t>(c.L.seg_off),
+                        c.at<uint64_t>(c.L.part_off), c.at<uint32_t>(c.L.item_tile),
+                        c.at<void>(c.L.seg_scan), c.s));
+    TRY(launch_splat(sa, splat_grid(c.L.n_tiles, npairs, seg_len), c.s));
+    TRY(c.prof.mark(5));
     return SPLOTCH_OK;
 }
 
@@ -427,8 +464,125 @@ splotch_status prepare(const splotch_particles *P, const splotch_camera *cam,
     if (!fit_capacity(P->n, cam, p, p->workspace_bytes, &c->L)) return SPLOTCH_E_WORKSPACE;
     c->ws = reinterpret_cast<char *>(p->workspace);
     c->s = reinterpret_cast<hipStream_t>(p->stream);
+    c->seg_min = p->seg_records > 0 ? (uint32_t)p->seg_records : kSegMin;
     if (c->prof.start(p->profile != 0 && p->stats != nullptr, c->s) != hipSuccess)
         return SPLOTCH_E_DEVICE;
+    return SPLOTCH_OK;
+}
+
+
+// ------------------------------------------------------------------ batch
+__global__ void k_copy_u64(const uint64_t *src, uint64_t *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::list<GraphEntry> g_graphs;  // most recently used first
+constexpr size_t kMaxGraphs = 16;
+
+void key_bytes(std::vector<uint64_t> *k, const void *p, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; i += 8) {
+        uint64_t w = 0;
+        memcpy(&w, b + i, std::min<size_t>(8, n - i));
+        k->push_back(w);
+    }
+}
+
+// Queue the whole batch on c.s without any host read-back.
+splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
+                             const splotch_camera *cams, const splotch_colourmap *cmap,
+                             const splotch_params *p, splotch_image *images) {
+    const int64_t n = P->n;
+    uint32_t *flags = c.at<uint32_t>(c.L.flags);
+    uint64_t *totals = reinterpret_cast<uint64_t *>(flags + SPLOTCH_MAX_VIEWS);
+    TRY(launch_fill_u32(flags, 0u, (size_t)nv, c.s));
+    const uint64_t cap = c.L.pair_cap;
+    const uint32_t nt = (uint32_t)(c.L.tile * c.L.tile);
+    for (int32_t v = 0; v < nv; ++v) {
+        const splotch_camera *cam = &cams[v];
+        Layout Lv = c.L;  // same buffers; per-view tile grid
+        Lv.ntx = (cam->width + c.L.tile - 1) / c.L.tile;
+        Lv.nty = (cam->height + c.L.tile - 1) / c.L.tile;
+        Lv.n_tiles = (uint32_t)(Lv.ntx * Lv.nty);
+        Ctx cv;  // fresh context (no stage events) over the same workspace
+        cv.L = Lv;
+        cv.ws = c.ws;
+        cv.s = c.s;
+        cv.seg_min = c.seg_min;
+        splotch_status st;
+        // the value range does not depend on the camera: the projection of
+        // every view recomputes it from the same particles
+        if ((st = run_project(cv, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
+            return st;
+        const uint32_t *order, *cnt_proc;
+        if ((st = run_order_and_scan(cv, n, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+        const uint64_t *total = c.at<uint64_t>(c.L.off) + n;
+        EmitArgs e;
+        e.rec = c.at<Rec>(c.L.rec);
+        e.order = order;
+        e.cnt = cnt_proc;
+        e.off = c.at<uint64_t>(c.L.off);
+        e.first = 0;
+        e.last = (uint64_t)n;
+        e.base = 0;
+        e.cap = cap;
+        e.overflow = flags + v;
+        e.tile = c.L.tile;
+        e.ntx = Lv.ntx;
+        uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
+        uint32_t *pv0 = c.at<uint32_t>(c.L.pv0), *pv1 = c.at<uint32_t>(c.L.pv1);
+        e.pair_key = pk0;
+        e.pair_val = pv0;
+        TRY(launch_emit(e, c.s));
+        hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, c.s, total, totals + v);
+        TRY(hipGetLastError());
+        int bits = 0;
+        while ((1ull << bits) < (uint64_t)Lv.n_tiles) ++bits;
+        bool in1 = false;
+        TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)cap, total, bits, true,
+                             c.at<void>(c.L.radix), &in1, c.s));
+        const uint32_t *keys = in1 ? pk1 : pk0;
+        const uint32_t *vals = in1 ? pv1 : pv0;
+        uint32_t *ts = c.at<uint32_t>(c.L.tstart), *te = c.at<uint32_t>(c.L.tend);
+        TRY(launch_tile_ranges(keys, (size_t)cap, total, ts, te, Lv.n_tiles, c.s));
+        TRY(launch_segments(ts, te, Lv.n_tiles, cap, total, nt, c.seg_min,
+                            c.at<uint32_t>(c.L.seg_len), c.at<uint32_t>(c.L.nseg),
+                            c.at<uint32_t>(c.L.nmulti), c.at<uint64_t>(c.L.seg_off),
+                            c.at<uint64_t>(c.L.part_off), c.at<uint32_t>(c.L.item_tile),
+                            c.at<void>(c.L.seg_scan), c.s));
+        SplatArgs sa;
+        memset(&sa, 0, sizeof sa);
+        sa.rec = c.at<Rec>(c.L.rec);
+        sa.pair_val = vals;
+        sa.tile_start = ts;
+        sa.tile_end = te;
+        sa.seg_off = c.at<uint64_t>(c.L.seg_off);
+        sa.part_off = c.at<uint64_t>(c.L.part_off);
+        sa.item_tile = c.at<uint32_t>(c.L.item_tile);
+        sa.partial = c.at<float>(c.L.partial);
+        sa.seg_len = c.at<uint32_t>(c.L.seg_len);
+        sa.palette = cmap->rgb;
+        sa.n_pal = cmap->n_entries;
+        sa.sp = species_dev(p);
+        sa.image = images[v].rgb;
+        sa.member_count = c.at<unsigned long long>(c.L.mcount);
+        sa.width = cam->width;
+        sa.height = cam->height;
+        sa.tile = c.L.tile;
+        sa.ntx = Lv.ntx;
+        sa.nty = Lv.nty;
+        sa.accumulate = p->accumulate;
+        sa.compensated = p->compensated ? 1 : 0;
+        sa.ordered = c.L.ordered ? 1 : 0;
+        const uint32_t q = 64;
+        const uint32_t grid = (uint32_t)((Lv.n_tiles + kSegTarget + q - 1) / q * q);
+        TRY(launch_splat(sa, grid, c.s));
+    }
     return SPLOTCH_OK;
 }
 
@@ -542,6 +696,11 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.compensated = p->compensated ? 1 : 0;
     sa.ordered = c.L.ordered ? 1 : 0;
     sa.member_count = c.at<unsigned long long>(c.L.mcount);
+    sa.seg_off = c.at<uint64_t>(c.L.seg_off);
+    sa.part_off = c.at<uint64_t>(c.L.part_off);
+    sa.item_tile = c.at<uint32_t>(c.L.item_tile);
+    sa.partial = c.at<float>(c.L.partial);
+    sa.seg_len = c.at<uint32_t>(c.L.seg_len);
     TRY(launch_fill_u32(c.at<uint32_t>(c.L.mcount), 0u, (size_t)c.L.n_tiles * 4, c.s));
 
     const uint64_t total = plan.back();
@@ -551,8 +710,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
         TRY(launch_fill_u32(c.at<uint32_t>(c.L.tend), 0u, c.L.n_tiles, c.s));
         sa.pair_val = c.at<uint32_t>(c.L.pv0);
         sa.accumulate = p->accumulate;
-        TRY(launch_splat(sa, c.s));
-        TRY(c.prof.mark(5));
+        if ((st = run_splat_pass(c, sa, 0)) != SPLOTCH_OK) return st;
         return read_stats(c, p, 0, 0);
     }
     // depth-ordered chunks are depth slabs: composite back to front
@@ -566,8 +724,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
             return st;
         sa.pair_val = vals;
         sa.accumulate = q == 0 ? p->accumulate : 1;
-        TRY(launch_splat(sa, c.s));
-        TRY(c.prof.mark(5));
+        if ((st = run_splat_pass(c, sa, o1 - o0)) != SPLOTCH_OK) return st;
     }
     return read_stats(c, p, (int64_t)total, nch);
 }
@@ -619,6 +776,108 @@ splotch_status splotch_bin(const splotch_particles *P, const splotch_camera *cam
     if (total > 0)
         TRY(hipMemcpyAsync(pair_particle, vals, (size_t)total * 4, hipMemcpyDeviceToDevice, c.s));
     return read_stats(c, p, (int64_t)total, 1);
+}
+
+splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
+                                    const splotch_camera *cams, const splotch_colourmap *cmap,
+                                    const splotch_params *p, splotch_image *images,
+                                    int32_t use_graph) {
+    if (n_views < 1 || n_views > SPLOTCH_MAX_VIEWS || !cams || !images || !p)
+        return SPLOTCH_E_INVALID_ARG;
+    if (use_graph != 0 && use_graph != 1) return SPLOTCH_E_INVALID_ARG;
+    splotch_status st;
+    int32_t big = 0;
+    uint64_t big_tiles = 0;
+    const int T = p->tile == 0 ? 16 : p->tile;
+    for (int32_t v = 0; v < n_views; ++v) {
+        if ((st = validate_camera(&cams[v])) != SPLOTCH_OK) return st;
+        if (!images[v].rgb || images[v].width != cams[v].width ||
+            images[v].height != cams[v].height)
+            return SPLOTCH_E_INVALID_ARG;
+        const uint64_t nt = (uint64_t)((cams[v].width + T - 1) / T) * ((cams[v].height + T - 1) / T);
+        if (nt > big_tiles) {
+            big_tiles = nt;
+            big = v;
+        }
+    }
+    if (!cmap || cmap->n_entries < 2 || !cmap->rgb) return SPLOTCH_E_INVALID_ARG;
+    Ctx c;
+    splotch_params q = *p;  // stats are read after the batch, not per stage
+    q.stats = nullptr;
+    if ((st = prepare(P, &cams[big], &q, &c)) != SPLOTCH_OK) return st;
+    if (use_graph && c.s == nullptr) return SPLOTCH_E_INVALID_ARG;
+    if (!use_graph) {
+        if ((st = enqueue_batch(c, P, n_views, cams, cmap, p, images)) != SPLOTCH_OK) return st;
+    } else {
+        std::vector<uint64_t> key;
+        key_bytes(&key, P, sizeof *P);
+        key_bytes(&key, cams, sizeof(splotch_camera) * (size_t)n_views);
+        key_bytes(&key, cmap, sizeof *cmap);
+        splotch_params kp = *p;
+        kp.stats = nullptr;
+        kp.stream = nullptr;
+        kp.profile = 0;
+        key_bytes(&key, &kp, sizeof kp);
+        key_bytes(&key, images, sizeof(splotch_image) * (size_t)n_views);
+        std::lock_guard<std::mutex> lock(g_graph_mu);
+        auto it = std::find_if(g_graphs.begin(), g_graphs.end(),
+                               [&](const GraphEntry &g) { return g.key == key; });
+        if (it == g_graphs.end()) {
+            hipGraph_t graph;
+            TRY(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+            st = enqueue_batch(c, P, n_views, cams, cmap, p, images);
+            hipError_t ec = hipStreamEndCapture(c.s, &graph);
+            if (st != SPLOTCH_OK) {
+                if (ec == hipSuccess) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            TRY(ec);
+            hipGraphExec_t exec;
+            hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            TRY(ei);
+            g_graphs.push_front(GraphEntry{key, exec});
+            if (g_graphs.size() > kMaxGraphs) {
+                (void)hipGraphExecDestroy(g_graphs.back().exec);
+                g_graphs.pop_back();
+            }
+            it = g_graphs.begin();
+        } else if (it != g_graphs.begin()) {
+            g_graphs.splice(g_graphs.begin(), g_graphs, it);
+            it = g_graphs.begin();
+        }
+        TRY(hipGraphLaunch(it->exec, c.s));
+    }
+    if (!p->stats) return SPLOTCH_OK;
+    std::vector<uint32_t> fl(n_views);
+    std::vector<uint64_t> tot(n_views);
+    uint32_t *flags = c.at<uint32_t>(c.L.flags);
+    TRY(hipMemcpyAsync(fl.data(), flags, 4 * (size_t)n_views, hipMemcpyDeviceToHost, c.s));
+    TRY(hipMemcpyAsync(tot.data(), flags + SPLOTCH_MAX_VIEWS, 8 * (size_t)n_views,
+                       hipMemcpyDeviceToHost, c.s));
+    TRY(hipStreamSynchronize(c.s));
+    bool over = false;
+    for (int32_t v = 0; v < n_views; ++v) {
+        splotch_stats *s = &p->stats[v];
+        memset(s, 0, sizeof *s);
+        s->n_pairs = (int64_t)tot[v];
+        s->n_chunks = fl[v] ? 0 : 1;
+        s->tile = c.L.tile;
+        s->ordered = c.L.ordered ? 1 : 0;
+        over = over || fl[v];
+    }
+    return over ? SPLOTCH_E_CAPACITY : SPLOTCH_OK;
+}
+
+int32_t splotch_graph_cache_clear(void) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    int32_t k = 0;
+    for (GraphEntry &g : g_graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        ++k;
+    }
+    g_graphs.clear();
+    return k;
 }
 
 }  // extern "C"

@@ -29,18 +29,27 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     const int tx0 = (int)(bb.x & kBboxMask) / T, tx1 = (int)((bb.x >> kBboxBits) & kBboxMask) / T;
     const int ty0 = (int)(bb.y & kBboxMask) / T, ty1 = (int)((bb.y >> kBboxBits) & kBboxMask) / T;
     uint64_t o = a.off[k] - a.base;
+    // Past the capacity (possible only where no host plan chunks the pass):
+    // write the pairs that fit, so every slot below the capacity holds a
+    // valid pair, and flag the pass.
+    if (o + c > a.cap && a.overflow) *a.overflow = 1u;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
+            if (o >= a.cap) return;
             a.pair_key[o] = (uint32_t)(ty * a.ntx + tx);
             a.pair_val[o] = i;
             ++o;
         }
 }
 
-__global__ void k_tile_ranges(const uint32_t *keys, size_t n, uint32_t *start, uint32_t *end) {
+__global__ void k_tile_ranges(const uint32_t *keys, size_t n_cap, const uint64_t *n_dev,
+                              uint32_t *start, uint32_t *end, uint32_t n_tiles) {
+    size_t n = n_cap;
+    if (n_dev && *n_dev < n) n = (size_t)*n_dev;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
         uint32_t key = keys[p];
+        if (key >= n_tiles) continue;  // cannot happen for emitted pairs; keeps stores in bounds
         if (p == 0 || keys[p - 1] != key) start[key] = (uint32_t)p;
         if (p == n - 1 || keys[p + 1] != key) end[key] = (uint32_t)(p + 1);
     }
@@ -107,14 +116,15 @@ hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs, uint32_t *start,
-                              uint32_t *end, uint32_t n_tiles, hipStream_t s) {
+hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs,
+                              const uint64_t *n_pairs_dev, uint32_t *start, uint32_t *end,
+                              uint32_t n_tiles, hipStream_t s) {
     hipError_t e = launch_fill_u32(start, 0u, n_tiles, s);
     if (e != hipSuccess) return e;
     e = launch_fill_u32(end, 0u, n_tiles, s);
     if (e != hipSuccess || n_pairs == 0) return e;
     hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(n_pairs, 1u << 20)), dim3(kThreads), 0, s,
-                       sorted_keys, n_pairs, start, end);
+                       sorted_keys, n_pairs, n_pairs_dev, start, end, n_tiles);
     return hipGetLastError();
 }
 

@@ -78,14 +78,16 @@ size_t scan_u32_scratch_bytes(size_t n);
 hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
-// vals_in may be null (values = 0..n-1).  Buffers k0/v0 hold the input;
+// vals_in may be null (values = 0..n-1).  With n_dev non-null the live
+// count is min(*n_dev, n) read on the device and n only sizes the grid
+// (graph-capturable).  Buffers k0/v0 hold the input;
 // k1/v1 are the second half of the ping-pong.  *result_in_1 tells which
 // half holds the output.  keys_needed = false lets the last pass skip
 // writing keys.
 size_t radix_scratch_bytes(size_t n);
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                            bool vals_identity, size_t n, int bits, bool keys_needed,
-                            void *scratch, bool *result_in_1, hipStream_t s);
+                            bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
+                            bool keys_needed, void *scratch, bool *result_in_1, hipStream_t s);
 
 // Binning.
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst,
@@ -97,20 +99,32 @@ struct EmitArgs {
     const uint64_t *off;     // pair offsets in processing order
     uint64_t first, last;    // processing positions [first, last)
     uint64_t base;           // off[first]
+    uint64_t cap;            // pair slots; a particle past it sets *overflow
+    uint32_t *overflow;      // may be null when cap is known to suffice
     int tile, ntx;
     uint32_t *pair_key, *pair_val;
 };
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
-hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs, uint32_t *start,
-                              uint32_t *end, uint32_t n_tiles, hipStream_t s);
+// n_pairs_dev (nullable): live pair count on the device, capped at n_pairs.
+hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs,
+                              const uint64_t *n_pairs_dev, uint32_t *start, uint32_t *end,
+                              uint32_t n_tiles, hipStream_t s);
 hipError_t launch_chunk_plan(const uint64_t *off, uint64_t n, uint64_t capacity,
                              uint64_t *bounds, uint32_t max_chunks, hipStream_t s);
 
-// Splat.
+// Splat.  Work items are (tile, segment): each tile's list is cut into
+// segments of at most seg_len records; a tile with one segment writes its
+// pixels directly, a tile with several writes one partial (C, Tr) per
+// segment that the merge kernel folds front to back.
 struct SplatArgs {
     const Rec *rec;
     const uint32_t *pair_val;
     const uint32_t *tile_start, *tile_end;
+    const uint64_t *seg_off;    // [n_tiles + 1] first item of each tile
+    const uint64_t *part_off;   // [n_tiles + 1] first partial slot of each multi-segment tile
+    const uint32_t *item_tile;  // item -> tile
+    float *partial;             // [slot][6][T*T]: C0 C1 C2 Tr0 Tr1 Tr2
+    const uint32_t *seg_len;    // device: records per segment for this pass
     const float *palette;
     int n_pal;
     SpeciesDev sp;
@@ -119,7 +133,27 @@ struct SplatArgs {
     int width, height, tile, ntx, nty;
     int accumulate, compensated, ordered;
 };
-hipError_t launch_splat(const SplatArgs &a, hipStream_t s);
+// Segment length rule (shared by host and device): a multiple of the
+// staging batch nt, at least seg_min, and at least pairs / kSegTarget so
+// that a pass has at most n_tiles + kSegTarget items.
+constexpr uint64_t kSegTarget = 8192;
+__host__ __device__ inline uint32_t seg_len_rule(uint64_t npairs, uint32_t nt, uint32_t seg_min) {
+    uint64_t s = (npairs + kSegTarget - 1) / kSegTarget;
+    if (s < seg_min) s = seg_min;
+    s = (s + nt - 1) / nt * nt;
+    return (uint32_t)(s < 0x7FFFFFFFull ? s : 0x7FFFFFFFull);
+}
+// Segment bookkeeping for one pass: segment length (from the pair count,
+// host value or device pointer), counts per tile, their scans and the
+// item -> tile map.  scratch: scan_u32_u64_scratch_bytes(n_tiles).
+hipError_t launch_segments(const uint32_t *tile_start, const uint32_t *tile_end,
+                           uint32_t n_tiles, uint64_t npairs, const uint64_t *npairs_dev,
+                           uint32_t nt, uint32_t seg_min, uint32_t *seg_len, uint32_t *nseg,
+                           uint32_t *nmulti, uint64_t *seg_off, uint64_t *part_off,
+                           uint32_t *item_tile, void *scratch, hipStream_t s);
+// Grid size (upper bound on items) for a pass with npairs pairs.
+uint32_t splat_grid(uint32_t n_tiles, uint64_t npairs, uint32_t seg_len);
+hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

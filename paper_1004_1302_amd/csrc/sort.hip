@@ -149,8 +149,16 @@ hipError_t scan_impl(const TI *in, TO *out, size_t n, TO *total_out, void *scrat
 }
 
 // ---------------------------------------------------------------- radix sort
-__global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n, int shift,
-                                                uint32_t *hist, uint32_t nblocks) {
+__device__ __forceinline__ size_t live_count(size_t n, const uint64_t *n_dev) {
+    if (!n_dev) return n;
+    const uint64_t d = *n_dev;
+    return d < n ? (size_t)d : n;
+}
+
+__global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_cap,
+                                                const uint64_t *n_dev, int shift, uint32_t *hist,
+                                                uint32_t nblocks) {
+    const size_t n = live_count(n_cap, n_dev);
     __shared__ uint32_t sh[kW][256];
     for (int d = threadIdx.x; d < kW * 256; d += kT) (&sh[0][0])[d] = 0;
     __syncthreads();
@@ -169,9 +177,12 @@ __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n, 
 }
 
 __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
-                                                   uint32_t *kout, uint32_t *vout, size_t n,
-                                                   int shift, const uint32_t *hist,
-                                                   uint32_t nblocks, int write_keys) {
+                                                   uint32_t *kout, uint32_t *vout, size_t n_cap,
+                                                   const uint64_t *n_dev, int shift,
+                                                   const uint32_t *hist, uint32_t nblocks,
+                                                   int write_keys) {
+    const size_t n = live_count(n_cap, n_dev);
+    if ((size_t)blockIdx.x * kTile >= n) return;  // whole block past the live count
     __shared__ uint32_t s_k[kTile], s_v[kTile];
     __shared__ uint32_t s_wc[kW][256];
     __shared__ uint32_t s_bs[256], s_go[256], s_sw[kW];
@@ -272,8 +283,8 @@ size_t radix_scratch_bytes(size_t n) {
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
-                            bool vals_identity, size_t n, int bits, bool keys_needed,
-                            void *scratch, bool *result_in_1, hipStream_t s) {
+                            bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
+                            bool keys_needed, void *scratch, bool *result_in_1, hipStream_t s) {
     *result_in_1 = false;
     if (n == 0) return hipSuccess;
     const uint32_t nb = (uint32_t)((n + kTile - 1) / kTile);
@@ -286,13 +297,13 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
         uint32_t *kout = src ? k0 : k1, *vout = src ? v0 : v1;
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kT), 0, s, kin, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kT), 0, s, kin, n, n_dev, shift, hist, nb);
         hipError_t e = launch_scan_u32(hist, (size_t)nb * 256, scan_scratch, s);
         if (e != hipSuccess) return e;
         const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kT), 0, s, kin,
                            (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin, kout,
-                           vout, n, shift, hist, nb, (!last || keys_needed) ? 1 : 0);
+                           vout, n, n_dev, shift, hist, nb, (!last || keys_needed) ? 1 : 0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         src ^= 1;

@@ -30,14 +30,21 @@ __device__ __forceinline__ float member_d2(int i, int i0, float ur, int j, int j
     return dx * dx + dy * dy;
 }
 
-// exp(-x) and phi(x) = (1 - exp(-x))/x.  For x < 1/32 both come from
-// their Taylor series (truncation below 3e-10), which keeps the product of
-// thousands of transmittance factors free of the bias a transcendental's
-// last-place error would add, and avoids the cancellation in 1 - exp(-x).
+// phi(x) = (1 - exp(-x))/x and exp(-x) = 1 - x phi(x).  For x < 1/32,
+// phi comes from its Taylor series (truncation below 3e-10) and exp(-x)
+// from one fused multiply-add: this keeps the product of thousands of
+// transmittance factors free of the bias a transcendental's last-place
+// error would add, and avoids the cancellation in 1 - exp(-x).
+constexpr float kSeriesMax = 0.03125f;
+
+__device__ __forceinline__ void ex_phi_small(float x, float &ex, float &ph) {
+    ph = 1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f))));
+    ex = __builtin_fmaf(-x, ph, 1.0f);
+}
+
 __device__ __forceinline__ void ex_phi(float x, float &ex, float &ph) {
-    if (x < 0.03125f) {
-        ex = 1.0f + x * (-1.0f + x * (0.5f + x * (-1.0f / 6.0f + x * (1.0f / 24.0f))));
-        ph = 1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f))));
+    if (x < kSeriesMax) {
+        ex_phi_small(x, ex, ph);
     } else {
         ex = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
         ph = (1.0f - ex) / x;
@@ -51,6 +58,33 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
+constexpr uint32_t kRun = 8;  // consecutive items per XCD run
+
+// Final pixel value: composite over the incoming image when accumulating.
+template <bool ORDERED>
+__device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, float C0, float C1,
+                                            float C2, float T0, float T1, float T2) {
+    if (i >= a.width || j >= a.height) return;
+    const size_t plane = (size_t)a.width * a.height;
+    const size_t o = (size_t)j * a.width + i;
+    float *img = a.image;
+    if (a.accumulate) {
+        const float in0 = img[o], in1 = img[plane + o], in2 = img[2 * plane + o];
+        if (ORDERED) {
+            C0 += T0 * in0;
+            C1 += T1 * in1;
+            C2 += T2 * in2;
+        } else {
+            C0 += in0;
+            C1 += in1;
+            C2 += in2;
+        }
+    }
+    img[o] = C0;
+    img[plane + o] = C1;
+    img[2 * plane + o] = C2;
+}
+
 template <int T, bool ORDERED, bool KAHAN>
 __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     constexpr int NT = T * T;
@@ -60,19 +94,26 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     __shared__ float s_e[3][NT];
     __shared__ float s_a[3][NT];
 
+    // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD runs of
+    // kRun consecutive items (neighbouring tiles share that XCD's L2) while
+    // the runs stay interleaved across XCDs (dense regions spread out).
+    const uint32_t b = blockIdx.x, k = b >> 3;
+    const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
-    const uint32_t per = gridDim.x / 8;
-    // workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-    // contiguous band of tiles so neighbouring tiles share its L2
-    const uint32_t tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (tile >= ntiles) return;
+    if (item >= a.seg_off[ntiles]) return;
+    const uint32_t tile = a.item_tile[item];
+    const uint32_t seg = item - (uint32_t)a.seg_off[tile];
+    const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
     const int tid = threadIdx.x;
     const int i = tx * T + (tid % T), j = ty * T + (tid / T);
     const int wave = tid >> 6;
     const int wx0 = tx * T, wx1 = tx * T + T - 1;
     const int wy0 = ty * T + wave * ROWS, wy1 = wy0 + ROWS - 1;
-    const uint32_t start = a.tile_start[tile], end = a.tile_end[tile];
+    const uint32_t seg_len = *a.seg_len;
+    const uint32_t tend = a.tile_end[tile];
+    const uint32_t start = a.tile_start[tile] + seg * seg_len;
+    const uint32_t end = (tend - start) > seg_len ? start + seg_len : tend;
 
     uint32_t n_member = 0, n_absorb = 0;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -114,10 +155,13 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
         __syncthreads();
         const int nb = (int)((end - base) < (uint32_t)NT ? (end - base) : (uint32_t)NT);
         for (int b = 0; b < nb; ++b) {
-            const uint32_t b0 = s_b0[b], b1 = s_b1[b];
+            // record fields are the same for every lane: decode and cull the
+            // footprint box in scalar registers
+            const uint32_t b0 = __builtin_amdgcn_readfirstlane(s_b0[b]);
+            const uint32_t b1 = __builtin_amdgcn_readfirstlane(s_b1[b]);
             const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
             const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
-            if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;  // wave-uniform
+            if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
             const float d2 = member_d2(i, i0, s_ur[b], j, j0, s_vr[b]);
             const bool in = i >= i0 && i <= i1 && j >= j0 && j <= j1 && d2 <= s_r2[b];
             if (!in) continue;
@@ -148,16 +192,29 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                 }
             } else {
                 ++n_absorb;
-                float ex, ph;
-                ex_phi(s_a[0][b] * w, ex, ph);
-                if (KAHAN) kahan_add(C0, K0, T0 * e0 * ph); else C0 += T0 * e0 * ph;
-                T0 *= ex;
-                ex_phi(s_a[1][b] * w, ex, ph);
-                if (KAHAN) kahan_add(C1, K1, T1 * e1 * ph); else C1 += T1 * e1 * ph;
-                T1 *= ex;
-                ex_phi(s_a[2][b] * w, ex, ph);
-                if (KAHAN) kahan_add(C2, K2, T2 * e2 * ph); else C2 += T2 * e2 * ph;
-                T2 *= ex;
+                const float x0 = s_a[0][b] * w, x1 = s_a[1][b] * w, x2 = s_a[2][b] * w;
+                float ex0, ex1, ex2, ph0, ph1, ph2;
+                if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
+                    ex_phi_small(x0, ex0, ph0);
+                    ex_phi_small(x1, ex1, ph1);
+                    ex_phi_small(x2, ex2, ph2);
+                } else {
+                    ex_phi(x0, ex0, ph0);
+                    ex_phi(x1, ex1, ph1);
+                    ex_phi(x2, ex2, ph2);
+                }
+                if (KAHAN) {
+                    kahan_add(C0, K0, T0 * (e0 * ph0));
+                    kahan_add(C1, K1, T1 * (e1 * ph1));
+                    kahan_add(C2, K2, T2 * (e2 * ph2));
+                } else {
+                    C0 += T0 * (e0 * ph0);
+                    C1 += T1 * (e1 * ph1);
+                    C2 += T2 * (e2 * ph2);
+                }
+                T0 *= ex0;
+                T1 *= ex1;
+                T2 *= ex2;
             }
         }
         __syncthreads();
@@ -180,56 +237,129 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
             t += s_cnt[0][w];
             ta += s_cnt[1][w];
         }
-        a.member_count[2 * tile] += t;
-        a.member_count[2 * tile + 1] += ta;
+        // statistics only; compositing itself uses no atomics
+        if (t) atomicAdd(&a.member_count[2 * tile], t);
+        if (ta) atomicAdd(&a.member_count[2 * tile + 1], ta);
     }
-    if (i < a.width && j < a.height) {
-        const size_t plane = (size_t)a.width * a.height;
-        const size_t o = (size_t)j * a.width + i;
-        float *img = a.image;
-        if (a.accumulate) {
-            const float in0 = img[o], in1 = img[plane + o], in2 = img[2 * plane + o];
-            if (ORDERED) {
-                C0 += T0 * in0;
-                C1 += T1 * in1;
-                C2 += T2 * in2;
-            } else {
-                C0 += in0;
-                C1 += in1;
-                C2 += in2;
-            }
+    if (nseg == 1) {
+        write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
+    } else {
+        float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
+        slot[0 * NT + tid] = C0;
+        slot[1 * NT + tid] = C1;
+        slot[2 * NT + tid] = C2;
+        if (ORDERED) {
+            slot[3 * NT + tid] = T0;
+            slot[4 * NT + tid] = T1;
+            slot[5 * NT + tid] = T2;
         }
-        img[o] = C0;
-        img[plane + o] = C1;
-        img[2 * plane + o] = C2;
     }
 }
 
-template <int T>
-hipError_t launch_t(const SplatArgs &a, hipStream_t s) {
-    const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
-    const uint32_t grid = (ntiles + 7) / 8 * 8;
-    if (a.ordered) {
-        if (a.compensated)
-            hipLaunchKernelGGL((k_splat<T, true, true>), dim3(grid), dim3(T * T), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_splat<T, true, false>), dim3(grid), dim3(T * T), 0, s, a);
-    } else {
-        if (a.compensated)
-            hipLaunchKernelGGL((k_splat<T, false, true>), dim3(grid), dim3(T * T), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_splat<T, false, false>), dim3(grid), dim3(T * T), 0, s, a);
+// Fold the partial (C, Tr) of a multi-segment tile front to back:
+// C += Tr * C_s, Tr *= Tr_s (the associative "over"); a plain sum when
+// nothing absorbs.
+template <int T, bool ORDERED, bool KAHAN>
+__global__ __launch_bounds__(T *T) void k_merge(SplatArgs a) {
+    constexpr int NT = T * T;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
+    if (nseg <= 1) return;
+    const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
+    const int tid = threadIdx.x;
+    const int i = tx * T + (tid % T), j = ty * T + (tid / T);
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
+    float T0 = 1.f, T1 = 1.f, T2 = 1.f;
+    const float *slot = a.partial + (size_t)a.part_off[tile] * 6 * NT;
+    for (uint32_t s = 0; s < nseg; ++s, slot += 6 * NT) {
+        const float c0 = slot[tid], c1 = slot[NT + tid], c2 = slot[2 * NT + tid];
+        if (KAHAN) {
+            kahan_add(C0, K0, ORDERED ? T0 * c0 : c0);
+            kahan_add(C1, K1, ORDERED ? T1 * c1 : c1);
+            kahan_add(C2, K2, ORDERED ? T2 * c2 : c2);
+        } else {
+            C0 += ORDERED ? T0 * c0 : c0;
+            C1 += ORDERED ? T1 * c1 : c1;
+            C2 += ORDERED ? T2 * c2 : c2;
+        }
+        if (ORDERED) {
+            T0 *= slot[3 * NT + tid];
+            T1 *= slot[4 * NT + tid];
+            T2 *= slot[5 * NT + tid];
+        }
     }
+    write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
+}
+
+__global__ void k_seg_count(const uint32_t *ts, const uint32_t *te, uint32_t n_tiles,
+                            uint64_t npairs, const uint64_t *npairs_dev, uint32_t nt,
+                            uint32_t seg_min, uint32_t *seg_len_out, uint32_t *nseg,
+                            uint32_t *nmulti) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t np = npairs_dev ? (*npairs_dev < npairs ? *npairs_dev : npairs) : npairs;
+    const uint32_t seg_len = seg_len_rule(np, nt, seg_min);
+    if (t == 0) *seg_len_out = seg_len;
+    if (t >= n_tiles) return;
+    const uint32_t len = te[t] - ts[t];
+    const uint32_t n = len == 0 ? 1u : (len + seg_len - 1) / seg_len;
+    nseg[t] = n;
+    nmulti[t] = n > 1 ? n : 0u;
+}
+
+__global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t *item_tile) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    for (uint64_t k = seg_off[t]; k < seg_off[t + 1]; ++k) item_tile[k] = t;
+}
+
+template <int T, bool ORDERED, bool KAHAN>
+hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_merge<T, ORDERED, KAHAN>), dim3((uint32_t)(a.ntx * a.nty)), dim3(T * T),
+                       0, s, a);
     return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_t(const SplatArgs &a, uint32_t grid, hipStream_t s) {
+    if (a.ordered)
+        return a.compensated ? launch_tok<T, true, true>(a, grid, s)
+                             : launch_tok<T, true, false>(a, grid, s);
+    return a.compensated ? launch_tok<T, false, true>(a, grid, s)
+                         : launch_tok<T, false, false>(a, grid, s);
 }
 
 }  // namespace
 
-hipError_t launch_splat(const SplatArgs &a, hipStream_t s) {
+uint32_t splat_grid(uint32_t n_tiles, uint64_t npairs, uint32_t seg_len) {
+    const uint64_t items = (uint64_t)n_tiles + (npairs + seg_len - 1) / seg_len;
+    const uint64_t q = 8 * kRun;
+    return (uint32_t)((items + q - 1) / q * q);
+}
+
+hipError_t launch_segments(const uint32_t *tile_start, const uint32_t *tile_end,
+                           uint32_t n_tiles, uint64_t npairs, const uint64_t *npairs_dev,
+                           uint32_t nt, uint32_t seg_min, uint32_t *seg_len, uint32_t *nseg,
+                           uint32_t *nmulti, uint64_t *seg_off, uint64_t *part_off,
+                           uint32_t *item_tile, void *scratch, hipStream_t s) {
+    const uint32_t g = (n_tiles + 255) / 256;
+    hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(256), 0, s, tile_start, tile_end, n_tiles,
+                       npairs, npairs_dev, nt, seg_min, seg_len, nseg, nmulti);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_scan_u32_u64(nseg, seg_off, n_tiles, scratch, s)) != hipSuccess) return e;
+    if ((e = launch_scan_u32_u64(nmulti, part_off, n_tiles, scratch, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_item_tiles, dim3(g), dim3(256), 0, s, seg_off, n_tiles, item_tile);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     switch (a.tile) {
-        case 8: return launch_t<8>(a, s);
-        case 16: return launch_t<16>(a, s);
-        case 32: return launch_t<32>(a, s);
+        case 8: return launch_t<8>(a, grid, s);
+        case 16: return launch_t<16>(a, grid, s);
+        case 32: return launch_t<32>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -161,3 +161,21 @@ def test_bin_and_project_validate():
     assert lib.splotch_project(C.byref(P), C.byref(cam), C.byref(prm), None, None, None, None, None) == 4
     n = C.c_int64()
     assert lib.splotch_bin(C.byref(P), C.byref(cam), C.byref(prm), None, None, None, 0, C.byref(n)) == 4
+
+
+def test_batch_validates_before_launch():
+    cam = B.camera_struct(synth.ortho_unit_square(64, 64))
+    prm = _params()
+    P = B.Particles()
+    cm = B.Colourmap(256, C.c_void_p(0x1000))
+    cams = (B.CameraS * 2)(cam, cam)
+    ims = (B.Image * 2)(B.Image(C.c_void_p(0x2000), 64, 64), B.Image(C.c_void_p(0x3000), 64, 64))
+    lib = B.lib()
+    assert lib.splotch_render_batch(C.byref(P), 0, cams, C.byref(cm), C.byref(prm), ims, 0) == 1
+    assert lib.splotch_render_batch(C.byref(P), 2, cams, C.byref(cm), None, ims, 0) == 1
+    bad = (B.Image * 2)(B.Image(C.c_void_p(0x2000), 64, 64), B.Image(C.c_void_p(0x3000), 32, 64))
+    assert lib.splotch_render_batch(C.byref(P), 2, cams, C.byref(cm), C.byref(prm), bad, 0) == 1
+    # no workspace
+    assert lib.splotch_render_batch(C.byref(P), 2, cams, C.byref(cm), C.byref(prm), ims, 0) == 2
+    assert lib.splotch_render_batch(C.byref(P), 2, cams, C.byref(cm), C.byref(prm), ims, 3) == 1
+    assert B.graph_cache_clear() == 0

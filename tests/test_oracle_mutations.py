@@ -45,7 +45,7 @@ def test_pins_catch_mutation(name, tmp_path):
     mut = tmp_path / "mut.c"
     mut.write_text(src.replace(old, new))
     lib = tmp_path / "libmut.so"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                            "-o", str(lib), str(mut), "-lm"])
     env = dict(os.environ, SPLOTCH_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
