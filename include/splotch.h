@@ -151,6 +151,10 @@ typedef struct splotch_params {
     int32_t seg_records; /* least records per tile-list segment (one workgroup
                             each); 0 = 1024.  Long lists are cut into segments
                             merged front to back; this only affects speed. */
+    const uint8_t *tile_mask; /* device, one byte per screen tile (row-major,
+                            tiles of params->tile px), or NULL = all tiles.
+                            Tiles whose byte is 0 are skipped: no pairs, no
+                            compositing, their pixels are left untouched. */
     void *stream;        /* hipStream_t */
     void *workspace;     /* device, >= splotch_workspace_size() bytes, 256-aligned */
     size_t workspace_bytes;
@@ -230,7 +234,8 @@ splotch_status splotch_bin(const splotch_particles *particles, const splotch_cam
  * splotch_workspace_size for the view with the most tiles; views are
  * rendered one after another through it.  There is no chunking: a view
  * whose pairs exceed the workspace's pair capacity is left incomplete and
- * flagged.  If params->stats is not NULL it must point to n_views structs;
+ * flagged.  params->tile_mask must be NULL (SPLOTCH_E_UNSUPPORTED).
+ * If params->stats is not NULL it must point to n_views structs;
  * the call then waits for the batch, fills n_pairs (and tile, ordered) per
  * view, and returns SPLOTCH_E_CAPACITY if any view overflowed (its
  * n_chunks is then 0).  Without stats the call returns as soon as the work
@@ -244,6 +249,98 @@ splotch_status splotch_render_batch(const splotch_particles *particles, int32_t 
 /* Destroy every cached HIP graph (see splotch_render_batch).  Returns the
  * number destroyed. */
 int32_t splotch_graph_cache_clear(void);
+
+/* ------------------------------------------------------------------------
+ * Learned decimation: kernels of the reconstruction network.  A render of
+ * a seeded 1/16 particle subset is mapped back towards the full render by
+ * a convolutional encoder-decoder trained on pairs this library renders.
+ * All pointers are device pointers; bf16 tensors are uint16 bit patterns
+ * (bfloat16, round to nearest even); activations are NHWC.  Every call is
+ * asynchronous on `stream`; argument errors return SPLOTCH_E_INVALID_ARG
+ * before any launch.
+ * ------------------------------------------------------------------------ */
+
+/* C[z][M][N] (float32) = sum over the z-th K range of A[m][k] * B[k][n]
+ * on BF16 matrix cores with FP32 accumulation.  A is [M][K] with row
+ * stride lda, or with trans_a = 1 stored as [K][M] (stride lda); B is
+ * [K][N] with stride ldb.  K is cut into splotch_nn_gemm_splits(K, splits)
+ * ranges; C must hold that many M x N slices (sum them with
+ * splotch_nn_epilogue). */
+splotch_status splotch_nn_gemm(const uint16_t *A, const uint16_t *B, float *C, int32_t M,
+                               int32_t N, int32_t K, int32_t lda, int32_t ldb, int32_t trans_a,
+                               int32_t splits, void *stream);
+int32_t splotch_nn_gemm_splits(int32_t K, int32_t splits);
+
+/* 3x3 patches with zero padding: out[p][tap*c + ch] = in[p + offset(tap)][ch],
+ * taps (ky, kx) row-major, p = (image, y, x); in is [n][h][w][c], c a
+ * multiple of 8; out is [n*h*w][9*c]. */
+splotch_status splotch_nn_im2col3x3(const uint16_t *in, uint16_t *out, int32_t n, int32_t h,
+                                    int32_t w, int32_t c, void *stream);
+
+/* Weights of the adjoint convolution.  Forward weights are the GEMM
+ * operand w[tap][ci][co] ([9*cin][cout]); the adjoint operand is
+ * wt[tap'][co][ci] = w[8-tap'][ci][co] ([9*cout][cin]). */
+splotch_status splotch_nn_flip_weights(const uint16_t *w, uint16_t *wt, int32_t cout, int32_t cin,
+                                       void *stream);
+
+/* out[r][c] = act(sum_z partials[z][r][c] + bias[c]) + residual[r][c];
+ * act = ReLU when relu, else identity; bias and residual may be NULL;
+ * writes out_bf16 and/or out_f32 (either may be NULL, not both). */
+splotch_status splotch_nn_epilogue(const float *partials, int32_t splits, int64_t rows,
+                                   int32_t cols, const float *bias, int32_t relu,
+                                   const float *residual, uint16_t *out_bf16, float *out_f32,
+                                   void *stream);
+
+/* ReLU adjoint: dz = dy where y > 0 (or everywhere when relu = 0), as bf16
+ * and optionally float32. */
+splotch_status splotch_nn_relu_bwd(const float *dy, const uint16_t *y, int32_t relu,
+                                   uint16_t *dz_bf16, float *dz_f32, int64_t n, void *stream);
+
+/* out[c] = sum over rows of in[row][c], cols <= 256 (bias gradients,
+ * image sums); scratch holds 1024 * cols floats. */
+splotch_status splotch_nn_colsum(const float *in, int64_t rows, int32_t cols, float *out,
+                                 float *scratch, void *stream);
+
+/* 2x2 average pool [n][h][w][c] -> [n][h/2][w/2][c] (bf16) and its adjoint
+ * (float32; accumulate adds into din). */
+splotch_status splotch_nn_pool2(const uint16_t *in, uint16_t *out, int32_t n, int32_t h, int32_t w,
+                                int32_t c, void *stream);
+splotch_status splotch_nn_pool2_bwd(const float *dout, float *din, int32_t n, int32_t h,
+                                    int32_t w, int32_t c, int32_t accumulate, void *stream);
+
+/* Nearest 2x upsample of a ([n][h/2][w/2][ca]) concatenated along channels
+ * with s ([n][h][w][cs]) into out ([n][h][w][ca+cs]), and its adjoint:
+ * da = 2x2 sums of the first ca channels, ds = the other cs channels. */
+splotch_status splotch_nn_up2_concat(const uint16_t *a, int32_t ca, const uint16_t *s, int32_t cs,
+                                     uint16_t *out, int32_t n, int32_t h, int32_t w,
+                                     void *stream);
+splotch_status splotch_nn_up2_concat_bwd(const float *dout, int32_t ca, int32_t cs, float *da,
+                                         float *ds, int32_t n, int32_t h, int32_t w,
+                                         void *stream);
+
+/* Mean squared error over the first `used` of c channels of [pixels][c]:
+ * grad = 2 (pred - target) / (pixels*used) (zero in unused channels);
+ * loss_partials[b] (nblocks floats) sum to the squared-error total. */
+splotch_status splotch_nn_mse(const float *pred, const float *target, float *grad, int64_t pixels,
+                              int32_t c, int32_t used, float *loss_partials, int32_t nblocks,
+                              void *stream);
+
+/* Adam step (bias-corrected, step >= 1) on float32 master weights w with
+ * moments m, v; also writes the bf16 copy when w_bf16 is not NULL. */
+splotch_status splotch_nn_adam(float *w, uint16_t *w_bf16, const float *g, float *m, float *v,
+                               int64_t n, float lr, float b1, float b2, float eps, int32_t step,
+                               void *stream);
+
+/* Tone map a planar [3][h][w] image into NHWC with c >= 3 channels (extra
+ * channels zero): out = log1p(max(img, 0) / scale); and back (first three
+ * channels): img = scale * expm1(in). */
+splotch_status splotch_nn_tonemap(const float *img, int32_t h, int32_t w, float scale, int32_t c,
+                                  float *out_f32, uint16_t *out_bf16, void *stream);
+splotch_status splotch_nn_untonemap(const float *in, int32_t h, int32_t w, float scale, int32_t c,
+                                    float *img, void *stream);
+
+/* float32 -> bfloat16 (round to nearest even). */
+splotch_status splotch_nn_f32_to_bf16(const float *in, uint16_t *out, int64_t n, void *stream);
 
 #ifdef __cplusplus
 }

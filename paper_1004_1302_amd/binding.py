@@ -75,6 +75,7 @@ class Params(C.Structure):
                 ("sigma_over_h", C.c_float), ("trunc_f", C.c_float),
                 ("accumulate", C.c_int32), ("compensated", C.c_int32), ("tile", C.c_int32),
                 ("profile", C.c_int32), ("seg_records", C.c_int32),
+                ("tile_mask", C.c_void_p),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats))]
 
@@ -87,7 +88,12 @@ _L = None
 
 EXPORTS = ("splotch_status_string", "splotch_camera_look_at", "splotch_workspace_size",
            "splotch_render", "splotch_project", "splotch_bin", "splotch_render_batch",
-           "splotch_graph_cache_clear")
+           "splotch_graph_cache_clear", "splotch_nn_gemm", "splotch_nn_gemm_splits",
+           "splotch_nn_im2col3x3", "splotch_nn_flip_weights", "splotch_nn_epilogue",
+           "splotch_nn_relu_bwd", "splotch_nn_colsum", "splotch_nn_pool2", "splotch_nn_pool2_bwd",
+           "splotch_nn_up2_concat", "splotch_nn_up2_concat_bwd", "splotch_nn_mse",
+           "splotch_nn_adam", "splotch_nn_tonemap", "splotch_nn_untonemap",
+           "splotch_nn_f32_to_bf16")
 MAX_VIEWS = 1024
 
 
@@ -168,7 +174,7 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 
 
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
-                  tile=0, profile=False, seg_records=0) -> Params:
+                  tile=0, profile=False, seg_records=0, tile_mask=None) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
@@ -183,6 +189,7 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.tile = int(tile)
     p.profile = 1 if profile else 0
     p.seg_records = int(seg_records)
+    p.tile_mask = None if tile_mask is None else C.c_void_p(tile_mask.data_ptr())
     return p
 
 
@@ -263,14 +270,15 @@ def _setup(parts, cam, species, max_pairs, workspace, **kw):
 
 def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, trunc_f=2.0,
            accumulate=False, compensated=False, tile=0, max_pairs=0, workspace=None,
-           stats=False, profile=False, seg_records=0):
+           stats=False, profile=False, seg_records=0, tile_mask=None):
     """Render into image (planar float32 [3, H, W] device tensor; allocated
     if None).  Returns the image, or (image, stats dict) with stats=True
     (profile=True adds per-stage milliseconds to the stats)."""
     import torch
     P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
                              trunc_f=trunc_f, accumulate=accumulate, compensated=compensated,
-                             tile=tile, profile=profile, seg_records=seg_records)
+                             tile=tile, profile=profile, seg_records=seg_records,
+                             tile_mask=tile_mask)
     stats = stats or profile
     if image is None:
         image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)

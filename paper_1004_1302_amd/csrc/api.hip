@@ -259,6 +259,7 @@ struct Ctx {
     char *ws;
     hipStream_t s;
     uint32_t seg_min = kSegMin;
+    const uint8_t *tile_mask = nullptr;
     Prof prof;
     template <typename T>
     T *at(size_t off) const {
@@ -285,6 +286,8 @@ splotch_status run_project(const Ctx &c, const splotch_particles *P, const splot
     a.soh = (double)p->sigma_over_h;
     a.f = (double)p->trunc_f;
     a.tile = c.L.tile;
+    a.ntx = c.L.ntx;
+    a.tile_mask = p->tile_mask;
     a.rec = c.at<Rec>(c.L.rec);
     a.cnt = c.at<uint32_t>(c.L.cnt);
     a.key = c.L.ordered ? c.at<uint32_t>(c.L.key0) : nullptr;
@@ -345,6 +348,7 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t
     e.base = off_first;
     e.cap = c.L.pair_cap;
     e.overflow = nullptr;
+    e.tile_mask = c.tile_mask;
     e.tile = c.L.tile;
     e.ntx = c.L.ntx;
     e.pair_key = pk0;
@@ -465,6 +469,7 @@ splotch_status prepare(const splotch_particles *P, const splotch_camera *cam,
     c->ws = reinterpret_cast<char *>(p->workspace);
     c->s = reinterpret_cast<hipStream_t>(p->stream);
     c->seg_min = p->seg_records > 0 ? (uint32_t)p->seg_records : kSegMin;
+    c->tile_mask = p->tile_mask;
     if (c->prof.start(p->profile != 0 && p->stats != nullptr, c->s) != hipSuccess)
         return SPLOTCH_E_DEVICE;
     return SPLOTCH_OK;
@@ -514,6 +519,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         cv.ws = c.ws;
         cv.s = c.s;
         cv.seg_min = c.seg_min;
+        cv.tile_mask = c.tile_mask;
         splotch_status st;
         // the value range does not depend on the camera: the projection of
         // every view recomputes it from the same particles
@@ -532,6 +538,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         e.base = 0;
         e.cap = cap;
         e.overflow = flags + v;
+        e.tile_mask = p->tile_mask;
         e.tile = c.L.tile;
         e.ntx = Lv.ntx;
         uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
@@ -571,6 +578,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         sa.sp = species_dev(p);
         sa.image = images[v].rgb;
         sa.member_count = c.at<unsigned long long>(c.L.mcount);
+        sa.tile_mask = p->tile_mask;
         sa.width = cam->width;
         sa.height = cam->height;
         sa.tile = c.L.tile;
@@ -696,6 +704,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.compensated = p->compensated ? 1 : 0;
     sa.ordered = c.L.ordered ? 1 : 0;
     sa.member_count = c.at<unsigned long long>(c.L.mcount);
+    sa.tile_mask = p->tile_mask;
     sa.seg_off = c.at<uint64_t>(c.L.seg_off);
     sa.part_off = c.at<uint64_t>(c.L.part_off);
     sa.item_tile = c.at<uint32_t>(c.L.item_tile);
@@ -785,6 +794,7 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
     if (n_views < 1 || n_views > SPLOTCH_MAX_VIEWS || !cams || !images || !p)
         return SPLOTCH_E_INVALID_ARG;
     if (use_graph != 0 && use_graph != 1) return SPLOTCH_E_INVALID_ARG;
+    if (p->tile_mask) return SPLOTCH_E_UNSUPPORTED;  // one mask cannot fit views of several sizes
     splotch_status st;
     int32_t big = 0;
     uint64_t big_tiles = 0;

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     if (o + c > a.cap && a.overflow) *a.overflow = 1u;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
+            if (a.tile_mask && !a.tile_mask[ty * a.ntx + tx]) continue;
             if (o >= a.cap) return;
             a.pair_key[o] = (uint32_t)(ty * a.ntx + tx);
             a.pair_val[o] = i;

@@ -50,7 +50,8 @@ struct ProjectArgs {
     const uint8_t *species;
     int64_t n;
     double soh, f;
-    int tile;
+    int tile, ntx;
+    const uint8_t *tile_mask;    // per tile, 0 = skip; null = all tiles
     const uint32_t *range_bits;  // [2*kMaxSpecies] ordered bits of auto min/max, or null
     Rec *rec;
     uint32_t *cnt;   // tile count per particle
@@ -102,6 +103,7 @@ struct EmitArgs {
     uint64_t cap;            // pair slots; a particle past it sets *overflow
     uint32_t *overflow;      // may be null when cap is known to suffice
     int tile, ntx;
+    const uint8_t *tile_mask;  // per tile, 0 = skip; null = all tiles
     uint32_t *pair_key, *pair_val;
 };
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
@@ -130,6 +132,7 @@ struct SplatArgs {
     SpeciesDev sp;
     float *image;
     unsigned long long *member_count;  // [2 per tile]: all, absorbing; summed over chunks
+    const uint8_t *tile_mask;          // per tile, 0 = leave untouched; null = all tiles
     int width, height, tile, ntx, nty;
     int accumulate, compensated, ordered;
 };

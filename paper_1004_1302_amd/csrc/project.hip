@@ -244,7 +244,13 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
             r.b.z = __float_as_uint(t);
             r.b.w = __float_as_uint(r0);
             a.rec[k] = r;
-            cnt = (uint32_t)((p.i1 / T - p.i0 / T + 1) * (p.j1 / T - p.j0 / T + 1));
+            if (!a.tile_mask) {
+                cnt = (uint32_t)((p.i1 / T - p.i0 / T + 1) * (p.j1 / T - p.j0 / T + 1));
+            } else {
+                for (int ty = p.j0 / T; ty <= p.j1 / T; ++ty)
+                    for (int tx = p.i0 / T; tx <= p.i1 / T; ++tx)
+                        cnt += a.tile_mask[ty * a.ntx + tx] ? 1u : 0u;
+            }
             key = order_bits((float)p.zc);
         }
         a.cnt[k] = cnt;

@@ -85,14 +85,24 @@ __device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, fl
     img[2 * plane + o] = C2;
 }
 
+// Records staged per batch: B indices of at most 8 bits per lane list.
+template <int T>
+struct Batch {
+    static constexpr int NT = T * T;
+    static constexpr int B = (32768 / NT) < 128 ? (32768 / NT) : 128;
+};
+
 template <int T, bool ORDERED, bool KAHAN>
 __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     constexpr int NT = T * T;
+    constexpr int B = Batch<T>::B;
     constexpr int ROWS = 64 / T;  // pixel rows per wave
-    __shared__ uint32_t s_b0[NT], s_b1[NT];
-    __shared__ float s_ur[NT], s_vr[NT], s_r2[NT], s_qs[NT];
-    __shared__ float s_e[3][NT];
-    __shared__ float s_a[3][NT];
+    __shared__ uint32_t s_b0[B], s_b1[B];
+    __shared__ float s_ur[B], s_vr[B], s_r2[B], s_qs[B];
+    __shared__ float s_e[3][B];
+    __shared__ float s_a[3][B];
+    // per-lane member lists: entry m of lane l at s_list[m * NT + l]
+    __shared__ uint8_t s_list[B * NT];
 
     // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD runs of
     // kRun consecutive items (neighbouring tiles share that XCD's L2) while
@@ -102,6 +112,7 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
     if (item >= a.seg_off[ntiles]) return;
     const uint32_t tile = a.item_tile[item];
+    if (a.tile_mask && !a.tile_mask[tile]) return;
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
@@ -120,66 +131,75 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
     float T0 = 1.f, T1 = 1.f, T2 = 1.f;
 
-    for (uint32_t base = start; base < end; base += NT) {
-        const uint32_t k = base + tid;
-        if (k < end) {
-            const uint32_t idx = a.pair_val[k];
-            const uint4 ra = a.rec[idx].a, rb = a.rec[idx].b;
-            const int sp = (int)(ra.x >> 28);
-            const float t = __uint_as_float(rb.z);
-            const float rho0 = __uint_as_float(rb.w);
-            const float pp = t * (float)(a.n_pal - 1);
-            int kk = (int)floorf(pp);
-            kk = kk > a.n_pal - 2 ? a.n_pal - 2 : kk;
-            const float w1 = pp - (float)kk, w0 = 1.0f - w1;
-            const float *c0 = a.palette + 3 * kk;
-            const float cr = c0[0] * w0 + c0[3] * w1;
-            const float cg = c0[1] * w0 + c0[4] * w1;
-            const float cb = c0[2] * w0 + c0[5] * w1;
-            const float eb = a.sp.brightness[sp] * rho0;
-            const bool ord = a.sp.ordered[sp] != 0;
-            const float ab = ord ? a.sp.absorption[sp] * rho0 : 0.0f;
-            s_b0[tid] = ra.x;
-            s_b1[tid] = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? 0x80000000u : 0u);
-            s_ur[tid] = __uint_as_float(ra.z);
-            s_vr[tid] = __uint_as_float(ra.w);
-            s_r2[tid] = __uint_as_float(rb.x);
-            s_qs[tid] = __uint_as_float(rb.y);
-            s_e[0][tid] = eb * cr;
-            s_e[1][tid] = eb * cg;
-            s_e[2][tid] = eb * cb;
-            s_a[0][tid] = ab * cr;
-            s_a[1][tid] = ab * cg;
-            s_a[2][tid] = ab * cb;
+    for (uint32_t base = start; base < end; base += B) {
+        // stage: gather records, expand colours once per record
+        for (int r = tid; r < B; r += NT) {
+            const uint32_t kk2 = base + r;
+            if (kk2 < end) {
+                const uint32_t idx = a.pair_val[kk2];
+                const uint4 ra = a.rec[idx].a, rb = a.rec[idx].b;
+                const int sp = (int)(ra.x >> 28);
+                const float t = __uint_as_float(rb.z);
+                const float rho0 = __uint_as_float(rb.w);
+                const float pp = t * (float)(a.n_pal - 1);
+                int kk = (int)floorf(pp);
+                kk = kk > a.n_pal - 2 ? a.n_pal - 2 : kk;
+                const float w1 = pp - (float)kk, w0 = 1.0f - w1;
+                const float *c0 = a.palette + 3 * kk;
+                const float cr = c0[0] * w0 + c0[3] * w1;
+                const float cg = c0[1] * w0 + c0[4] * w1;
+                const float cb = c0[2] * w0 + c0[5] * w1;
+                const float eb = a.sp.brightness[sp] * rho0;
+                const bool ord = a.sp.ordered[sp] != 0;
+                const float ab = ord ? a.sp.absorption[sp] * rho0 : 0.0f;
+                s_b0[r] = ra.x;
+                s_b1[r] = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? 0x80000000u : 0u);
+                s_ur[r] = __uint_as_float(ra.z);
+                s_vr[r] = __uint_as_float(ra.w);
+                s_r2[r] = __uint_as_float(rb.x);
+                s_qs[r] = __uint_as_float(rb.y);
+                s_e[0][r] = eb * cr;
+                s_e[1][r] = eb * cg;
+                s_e[2][r] = eb * cb;
+                s_a[0][r] = ab * cr;
+                s_a[1][r] = ab * cg;
+                s_a[2][r] = ab * cb;
+            }
         }
         __syncthreads();
-        const int nb = (int)((end - base) < (uint32_t)NT ? (end - base) : (uint32_t)NT);
-        for (int b = 0; b < nb; ++b) {
+        const int nb = (int)((end - base) < (uint32_t)B ? (end - base) : (uint32_t)B);
+        // phase 1: each lane lists, in order, the staged records whose
+        // footprint holds its pixel (binary32 membership of the index recipe)
+        int cnt = 0;
+        for (int r = 0; r < nb; ++r) {
             // record fields are the same for every lane: decode and cull the
             // footprint box in scalar registers
-            const uint32_t b0 = __builtin_amdgcn_readfirstlane(s_b0[b]);
-            const uint32_t b1 = __builtin_amdgcn_readfirstlane(s_b1[b]);
+            const uint32_t b0 = __builtin_amdgcn_readfirstlane(s_b0[r]);
+            const uint32_t b1 = __builtin_amdgcn_readfirstlane(s_b1[r]);
             const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
             const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
             if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
-            const float d2 = member_d2(i, i0, s_ur[b], j, j0, s_vr[b]);
-            const bool in = i >= i0 && i <= i1 && j >= j0 && j <= j1 && d2 <= s_r2[b];
-            if (!in) continue;
-            ++n_member;
-            const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[b]);  // exp(-q^2)
-            const float e0 = s_e[0][b] * w, e1 = s_e[1][b] * w, e2 = s_e[2][b] * w;
-            if (!ORDERED || (b1 >> 31)) {
-                if (ORDERED) {
-                    if (KAHAN) {
-                        kahan_add(C0, K0, T0 * e0);
-                        kahan_add(C1, K1, T1 * e1);
-                        kahan_add(C2, K2, T2 * e2);
-                    } else {
-                        C0 += T0 * e0;
-                        C1 += T1 * e1;
-                        C2 += T2 * e2;
-                    }
-                } else {
+            const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
+            const bool in = i >= i0 && i <= i1 && j >= j0 && j <= j1 && d2 <= s_r2[r];
+            if (in) {
+                s_list[cnt * NT + tid] = (uint8_t)r;
+                ++cnt;
+            }
+        }
+        // phase 2: composite each lane's list front to back; lanes work on
+        // different records at once, so every active lane does useful work.
+        // Emission-only records take the same path: with A = 0 the series
+        // gives phi = 1 and exp(-x) = 1 exactly.
+        for (int m = 0; __ballot(m < cnt) != 0ull; ++m) {
+            if (m < cnt) {
+                const int r = s_list[m * NT + tid];
+                const uint32_t b0 = s_b0[r], b1 = s_b1[r];
+                const int i0 = (int)(b0 & kBboxMask), j0 = (int)(b1 & kBboxMask);
+                const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
+                const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[r]);  // exp(-q^2)
+                const float e0 = s_e[0][r] * w, e1 = s_e[1][r] * w, e2 = s_e[2][r] * w;
+                ++n_member;
+                if (!ORDERED) {
                     if (KAHAN) {
                         kahan_add(C0, K0, e0);
                         kahan_add(C1, K1, e1);
@@ -189,32 +209,32 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                         C1 += e1;
                         C2 += e2;
                     }
-                }
-            } else {
-                ++n_absorb;
-                const float x0 = s_a[0][b] * w, x1 = s_a[1][b] * w, x2 = s_a[2][b] * w;
-                float ex0, ex1, ex2, ph0, ph1, ph2;
-                if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
-                    ex_phi_small(x0, ex0, ph0);
-                    ex_phi_small(x1, ex1, ph1);
-                    ex_phi_small(x2, ex2, ph2);
                 } else {
-                    ex_phi(x0, ex0, ph0);
-                    ex_phi(x1, ex1, ph1);
-                    ex_phi(x2, ex2, ph2);
+                    n_absorb += (b1 >> 31) ^ 1u;
+                    const float x0 = s_a[0][r] * w, x1 = s_a[1][r] * w, x2 = s_a[2][r] * w;
+                    float ex0, ex1, ex2, ph0, ph1, ph2;
+                    if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
+                        ex_phi_small(x0, ex0, ph0);
+                        ex_phi_small(x1, ex1, ph1);
+                        ex_phi_small(x2, ex2, ph2);
+                    } else {
+                        ex_phi(x0, ex0, ph0);
+                        ex_phi(x1, ex1, ph1);
+                        ex_phi(x2, ex2, ph2);
+                    }
+                    if (KAHAN) {
+                        kahan_add(C0, K0, T0 * (e0 * ph0));
+                        kahan_add(C1, K1, T1 * (e1 * ph1));
+                        kahan_add(C2, K2, T2 * (e2 * ph2));
+                    } else {
+                        C0 += T0 * (e0 * ph0);
+                        C1 += T1 * (e1 * ph1);
+                        C2 += T2 * (e2 * ph2);
+                    }
+                    T0 *= ex0;
+                    T1 *= ex1;
+                    T2 *= ex2;
                 }
-                if (KAHAN) {
-                    kahan_add(C0, K0, T0 * (e0 * ph0));
-                    kahan_add(C1, K1, T1 * (e1 * ph1));
-                    kahan_add(C2, K2, T2 * (e2 * ph2));
-                } else {
-                    C0 += T0 * (e0 * ph0);
-                    C1 += T1 * (e1 * ph1);
-                    C2 += T2 * (e2 * ph2);
-                }
-                T0 *= ex0;
-                T1 *= ex1;
-                T2 *= ex2;
             }
         }
         __syncthreads();
@@ -264,7 +284,7 @@ __global__ __launch_bounds__(T *T) void k_merge(SplatArgs a) {
     constexpr int NT = T * T;
     const uint32_t tile = blockIdx.x;
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
-    if (nseg <= 1) return;
+    if (nseg <= 1 || (a.tile_mask && !a.tile_mask[tile])) return;
     const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
     const int tid = threadIdx.x;
     const int i = tx * T + (tid % T), j = ty * T + (tid / T);

@@ -1,0 +1,491 @@
+"""Learned decimation: render a seeded 1/16 subset of the particles and
+reconstruct the full render with a convolutional encoder-decoder; fall back
+to the full render when a cheap probe says the reconstruction is not good
+enough.
+
+Every arithmetic step runs in libsplotch's HIP kernels (the render, the
+BF16 matrix-core GEMM behind each 3x3 convolution, im2col, epilogues,
+pooling, upsampling, loss, Adam, tone mapping); torch only holds the
+buffers and the stream.
+
+Network: six levels with 32, 32, 64, 64, 128, 128 channels.  Each level has
+two 3x3 convolutions with ReLU; the encoder halves the resolution with 2x2
+average pooling, the decoder doubles it with nearest upsampling and
+concatenates the encoder features of the same level; a final 3x3
+convolution (no activation) adds a correction to the tone-mapped input:
+    x = log1p(I_dec / s),  y = x + net(x),  I = s * expm1(y),
+s being the mean of the decimated render.  About 1.46M parameters.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import binding as B
+
+LEVELS = (32, 32, 64, 64, 128, 128)
+CIN = 32          # tone-mapped RGB, zero-padded to a matrix-core friendly width
+DECIMATE = 16     # keep 1 particle in 16
+H_SCALE = DECIMATE ** (1.0 / 3.0)
+
+_declared = False
+
+
+def _lib():
+    global _declared
+    L = B.lib()
+    if not _declared:
+        P, I32, I64, F32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+        sig = {
+            "splotch_nn_gemm": [P, P, P, I32, I32, I32, I32, I32, I32, I32, P],
+            "splotch_nn_im2col3x3": [P, P, I32, I32, I32, I32, P],
+            "splotch_nn_flip_weights": [P, P, I32, I32, P],
+            "splotch_nn_epilogue": [P, I32, I64, I32, P, I32, P, P, P, P],
+            "splotch_nn_relu_bwd": [P, P, I32, P, P, I64, P],
+            "splotch_nn_colsum": [P, I64, I32, P, P, P],
+            "splotch_nn_pool2": [P, P, I32, I32, I32, I32, P],
+            "splotch_nn_pool2_bwd": [P, P, I32, I32, I32, I32, I32, P],
+            "splotch_nn_up2_concat": [P, I32, P, I32, P, I32, I32, I32, P],
+            "splotch_nn_up2_concat_bwd": [P, I32, I32, P, P, I32, I32, I32, P],
+            "splotch_nn_mse": [P, P, P, I64, I32, I32, P, I32, P],
+            "splotch_nn_adam": [P, P, P, P, P, I64, F32, F32, F32, F32, I32, P],
+            "splotch_nn_tonemap": [P, I32, I32, F32, I32, P, P, P],
+            "splotch_nn_untonemap": [P, I32, I32, F32, I32, P, P],
+            "splotch_nn_f32_to_bf16": [P, P, I64, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.restype = C.c_int
+            fn.argtypes = args
+        L.splotch_nn_gemm_splits.restype = C.c_int32
+        L.splotch_nn_gemm_splits.argtypes = [C.c_int32, C.c_int32]
+        _declared = True
+    return L
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _s():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ok(code, what):
+    if code != 0:
+        raise B.SplotchError(code, what)
+
+
+# ------------------------------------------------------------------ ops
+class Ops:
+    """Thin wrappers over the C ABI; tensors are torch device tensors
+    (bf16 data held as int16 bit patterns)."""
+
+    def __init__(self):
+        self.L = _lib()
+
+    def gemm(self, A, Bm, Cbuf, M, N, K, lda, ldb, trans_a, splits):
+        _ok(self.L.splotch_nn_gemm(_p(A), _p(Bm), _p(Cbuf), M, N, K, lda, ldb, trans_a, splits,
+                                   _s()), "nn_gemm")
+
+    def splits(self, K, want):
+        return int(self.L.splotch_nn_gemm_splits(K, want))
+
+    def im2col(self, x, col, n, h, w, c):
+        _ok(self.L.splotch_nn_im2col3x3(_p(x), _p(col), n, h, w, c, _s()), "nn_im2col3x3")
+
+    def flip(self, w, wt, cout, cin):
+        _ok(self.L.splotch_nn_flip_weights(_p(w), _p(wt), cout, cin, _s()), "nn_flip_weights")
+
+    def epilogue(self, Cp, splits, rows, cols, bias, relu, residual, out_bf, out_f):
+        _ok(self.L.splotch_nn_epilogue(_p(Cp), splits, rows, cols, _p(bias), int(relu),
+                                       _p(residual), _p(out_bf), _p(out_f), _s()), "nn_epilogue")
+
+    def relu_bwd(self, dy, y, relu, dz_bf, dz_f, n):
+        _ok(self.L.splotch_nn_relu_bwd(_p(dy), _p(y), int(relu), _p(dz_bf), _p(dz_f), n, _s()),
+            "nn_relu_bwd")
+
+    def colsum(self, x, rows, cols, out, scratch):
+        _ok(self.L.splotch_nn_colsum(_p(x), rows, cols, _p(out), _p(scratch), _s()), "nn_colsum")
+
+    def pool2(self, x, out, n, h, w, c):
+        _ok(self.L.splotch_nn_pool2(_p(x), _p(out), n, h, w, c, _s()), "nn_pool2")
+
+    def pool2_bwd(self, dout, din, n, h, w, c, acc):
+        _ok(self.L.splotch_nn_pool2_bwd(_p(dout), _p(din), n, h, w, c, int(acc), _s()),
+            "nn_pool2_bwd")
+
+    def up2_concat(self, a, ca, sk, cs, out, n, h, w):
+        _ok(self.L.splotch_nn_up2_concat(_p(a), ca, _p(sk), cs, _p(out), n, h, w, _s()),
+            "nn_up2_concat")
+
+    def up2_concat_bwd(self, dout, ca, cs, da, ds, n, h, w):
+        _ok(self.L.splotch_nn_up2_concat_bwd(_p(dout), ca, cs, _p(da), _p(ds), n, h, w, _s()),
+            "nn_up2_concat_bwd")
+
+    def mse(self, pred, target, grad, pixels, c, used, part, nblocks):
+        _ok(self.L.splotch_nn_mse(_p(pred), _p(target), _p(grad), pixels, c, used, _p(part),
+                                  nblocks, _s()), "nn_mse")
+
+    def adam(self, w, w_bf, g, m, v, n, lr, b1, b2, eps, step):
+        _ok(self.L.splotch_nn_adam(_p(w), _p(w_bf), _p(g), _p(m), _p(v), n, lr, b1, b2, eps, step,
+                                   _s()), "nn_adam")
+
+    def tonemap(self, img, h, w, scale, c, out_f, out_bf):
+        _ok(self.L.splotch_nn_tonemap(_p(img), h, w, float(scale), c, _p(out_f), _p(out_bf),
+                                      _s()), "nn_tonemap")
+
+    def untonemap(self, x, h, w, scale, c, img):
+        _ok(self.L.splotch_nn_untonemap(_p(x), h, w, float(scale), c, _p(img), _s()),
+            "nn_untonemap")
+
+    def f2bf(self, x, out, n):
+        _ok(self.L.splotch_nn_f32_to_bf16(_p(x), _p(out), n, _s()), "nn_f32_to_bf16")
+
+
+class Scratch:
+    """Named, grow-only device buffers."""
+
+    def __init__(self, device):
+        self.dev = device
+        self.bufs = {}
+
+    def get(self, name, numel, dtype):
+        import torch
+        t = self.bufs.get(name)
+        if t is None or t.numel() < numel or t.dtype != dtype:
+            t = torch.empty(max(numel, 1), dtype=dtype, device=self.dev)
+            self.bufs[name] = t
+        return t[:numel]
+
+
+# ------------------------------------------------------------------ layers
+class Conv3x3:
+    """3x3 convolution, stride 1, zero padding.  Master weights in FP32 laid
+    out as the GEMM operand [9*cin][cout] (tap-major, then input channel),
+    with a BF16 copy; FP32 bias; Adam moments."""
+
+    def __init__(self, cin, cout, relu, rng, device, gain=1.0):
+        import torch
+        self.cin, self.cout, self.relu = cin, cout, relu
+        std = gain * math.sqrt(2.0 / (9 * cin))
+        w = rng.standard_normal((9 * cin, cout)) * std
+        self.w = torch.from_numpy(w.astype(np.float32)).to(device)
+        self.b = torch.zeros(cout, dtype=torch.float32, device=device)
+        self.w_bf = torch.empty((9 * cin, cout), dtype=torch.int16, device=device)
+        self.wt_bf = torch.empty((9 * cout, cin), dtype=torch.int16, device=device)
+        self.gw = torch.empty_like(self.w)
+        self.gb = torch.empty_like(self.b)
+        self.mw = torch.zeros_like(self.w)
+        self.vw = torch.zeros_like(self.w)
+        self.mb = torch.zeros_like(self.b)
+        self.vb = torch.zeros_like(self.b)
+        self.ops = Ops()
+        self.ops.f2bf(self.w, self.w_bf, self.w.numel())
+
+    def n_params(self):
+        return self.w.numel() + self.b.numel()
+
+    def forward(self, x_bf, n, h, w, out_bf, sc, tag, out_f=None, residual=None):
+        P = n * h * w
+        col = sc.get("col", P * 9 * self.cin, self.w_bf.dtype)
+        self.ops.im2col(x_bf, col, n, h, w, self.cin)
+        cbuf = sc.get("gemm", P * self.cout, self.w.dtype)
+        self.ops.gemm(col, self.w_bf, cbuf, P, self.cout, 9 * self.cin, 9 * self.cin, self.cout,
+                      0, 1)
+        self.ops.epilogue(cbuf, 1, P, self.cout, self.b, self.relu, residual, out_bf, out_f)
+
+    def backward(self, x_bf, y_bf, dy, n, h, w, sc, need_dx):
+        """dy: FP32 gradient of this layer's output.  Fills gw, gb and returns
+        the FP32 gradient of its input (or None)."""
+        P = n * h * w
+        dz_bf = sc.get("dz_bf", P * self.cout, self.w_bf.dtype)
+        dz_f = sc.get("dz_f", P * self.cout, self.w.dtype)
+        self.ops.relu_bwd(dy, y_bf, self.relu, dz_bf, dz_f, P * self.cout)
+        self.ops.colsum(dz_f, P, self.cout, self.gb,
+                        sc.get("colsum", 1024 * self.cout, self.w.dtype))
+        col = sc.get("col", P * 9 * self.cin, self.w_bf.dtype)
+        self.ops.im2col(x_bf, col, n, h, w, self.cin)
+        want = max(1, min(256, P // 2048))
+        splits = self.ops.splits(P, want)
+        cw = sc.get("gemm_w", splits * 9 * self.cin * self.cout, self.w.dtype)
+        self.ops.gemm(col, dz_bf, cw, 9 * self.cin, self.cout, P, 9 * self.cin, self.cout, 1, want)
+        self.ops.epilogue(cw, splits, 9 * self.cin, self.cout, None, 0, None, None, self.gw)
+        if not need_dx:
+            return None
+        self.ops.flip(self.w_bf, self.wt_bf, self.cout, self.cin)
+        colz = sc.get("colz", P * 9 * self.cout, self.w_bf.dtype)
+        self.ops.im2col(dz_bf, colz, n, h, w, self.cout)
+        dx = sc.get(f"dx_{id(self)}", P * self.cin, self.w.dtype)
+        self.ops.gemm(colz, self.wt_bf, dx, P, self.cin, 9 * self.cout, 9 * self.cout, self.cin,
+                      0, 1)
+        return dx
+
+    def adam(self, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self.ops.adam(self.w, self.w_bf, self.gw, self.mw, self.vw, self.w.numel(), lr, b1, b2,
+                      eps, step)
+        self.ops.adam(self.b, None, self.gb, self.mb, self.vb, self.b.numel(), lr, b1, b2, eps,
+                      step)
+
+
+class UNet:
+    """Six-level encoder-decoder on NHWC BF16 activations."""
+
+    def __init__(self, seed=0, device="cuda", levels=LEVELS):
+        rng = np.random.default_rng(seed)
+        self.levels = levels
+        self.dev = device
+        L = len(levels)
+        self.enc = []
+        for l in range(L):
+            cin = CIN if l == 0 else levels[l - 1]
+            self.enc.append((Conv3x3(cin, levels[l], True, rng, device),
+                             Conv3x3(levels[l], levels[l], True, rng, device)))
+        self.dec = [None] * (L - 1)
+        for l in range(L - 2, -1, -1):
+            cin = levels[l + 1] + levels[l]
+            self.dec[l] = (Conv3x3(cin, levels[l], True, rng, device),
+                           Conv3x3(levels[l], levels[l], True, rng, device))
+        self.out = Conv3x3(levels[0], CIN, False, rng, device, gain=0.1)
+        self.ops = Ops()
+        self.sc = Scratch(device)
+        self.step = 0
+
+    def layers(self):
+        out = [c for pair in self.enc for c in pair]
+        out += [c for pair in self.dec for c in pair]
+        return out + [self.out]
+
+    def n_params(self):
+        return sum(c.n_params() for c in self.layers())
+
+    def _act(self, name, numel):
+        import torch
+        return self.sc.get(name, numel, torch.int16)
+
+    def _f(self, name, numel):
+        import torch
+        return self.sc.get(name, numel, torch.float32)
+
+    def forward(self, x_f, x_bf, n, h, w):
+        """x_f, x_bf: tone-mapped input [n*h*w, 32] (FP32 and BF16).  Returns
+        the FP32 output [n*h*w, 32] (first three channels meaningful)."""
+        L = len(self.levels)
+        self.shape = (n, h, w)
+        sizes = [(h >> l, w >> l) for l in range(L)]
+        self.saved = {}
+        inp = x_bf
+        for l in range(L):
+            hh, ww = sizes[l]
+            P = n * hh * ww
+            c = self.levels[l]
+            if l > 0:
+                pin = self._act(f"pool{l}", P * self.levels[l - 1])
+                self.ops.pool2(self.saved[f"e{l - 1}"], pin, n, 2 * hh, 2 * ww, self.levels[l - 1])
+                inp = pin
+            a = self._act(f"ea{l}", P * c)
+            e = self._act(f"e{l}", P * c)
+            self.enc[l][0].forward(inp, n, hh, ww, a, self.sc, f"enc{l}a")
+            self.enc[l][1].forward(a, n, hh, ww, e, self.sc, f"enc{l}b")
+            self.saved[f"ein{l}"] = inp
+            self.saved[f"ea{l}"] = a
+            self.saved[f"e{l}"] = e
+        d = self.saved[f"e{L - 1}"]
+        for l in range(L - 2, -1, -1):
+            hh, ww = sizes[l]
+            P = n * hh * ww
+            c = self.levels[l]
+            cat = self._act(f"cat{l}", P * (self.levels[l + 1] + c))
+            self.ops.up2_concat(d, self.levels[l + 1], self.saved[f"e{l}"], c, cat, n, hh, ww)
+            a = self._act(f"da{l}", P * c)
+            dd = self._act(f"d{l}", P * c)
+            self.dec[l][0].forward(cat, n, hh, ww, a, self.sc, f"dec{l}a")
+            self.dec[l][1].forward(a, n, hh, ww, dd, self.sc, f"dec{l}b")
+            self.saved[f"cat{l}"] = cat
+            self.saved[f"da{l}"] = a
+            self.saved[f"d{l}"] = dd
+            d = dd
+        P0 = n * h * w
+        y = self._f("y", P0 * CIN)
+        self.out.forward(d, n, h, w, None, self.sc, "out", out_f=y, residual=x_f)
+        self.saved["x_bf"] = x_bf
+        return y
+
+    def backward(self, gy):
+        """gy: FP32 gradient of the output [n*h*w, 32].  Fills every layer's
+        weight and bias gradients."""
+        n, h, w = self.shape
+        L = len(self.levels)
+        sizes = [(h >> l, w >> l) for l in range(L)]
+        ge = [None] * L
+        gd = self.out.backward(self.saved["d0"], None, gy, n, h, w, self.sc, True)
+        for l in range(L - 1):
+            hh, ww = sizes[l]
+            c = self.levels[l]
+            g = self.dec[l][1].backward(self.saved[f"da{l}"], self.saved[f"d{l}"], gd, n, hh, ww,
+                                        self.sc, True)
+            g = self.dec[l][0].backward(self.saved[f"cat{l}"], self.saved[f"da{l}"], g, n, hh, ww,
+                                        self.sc, True)
+            hl, wl = sizes[l + 1]
+            gd_next = self._f(f"gdn{l}", n * hl * wl * self.levels[l + 1])
+            ge[l] = self._f(f"ge{l}", n * hh * ww * c)
+            self.ops.up2_concat_bwd(g, self.levels[l + 1], c, gd_next, ge[l], n, hh, ww)
+            gd = gd_next
+        ge[L - 1] = gd
+        for l in range(L - 1, -1, -1):
+            hh, ww = sizes[l]
+            g = self.enc[l][1].backward(self.saved[f"ea{l}"], self.saved[f"e{l}"], ge[l], n, hh,
+                                        ww, self.sc, True)
+            g = self.enc[l][0].backward(self.saved[f"ein{l}"], self.saved[f"ea{l}"], g, n, hh, ww,
+                                        self.sc, l > 0)
+            if l > 0:
+                self.ops.pool2_bwd(g, ge[l - 1], n, 2 * hh, 2 * ww, self.levels[l - 1], True)
+
+    def adam_step(self, lr):
+        self.step += 1
+        for c in self.layers():
+            c.adam(self.step, lr)
+
+    def state_dict(self):
+        d = {}
+        for k, c in enumerate(self.layers()):
+            d[f"w{k}"] = c.w.cpu().numpy()
+            d[f"b{k}"] = c.b.cpu().numpy()
+        return d
+
+    def load_state_dict(self, d):
+        import torch
+        for k, c in enumerate(self.layers()):
+            c.w.copy_(torch.from_numpy(d[f"w{k}"]))
+            c.b.copy_(torch.from_numpy(d[f"b{k}"]))
+            c.ops.f2bf(c.w, c.w_bf, c.w.numel())
+
+
+# ------------------------------------------------------------------ data
+def decimate(parts: dict, seed=7, keep=DECIMATE):
+    """Seeded 1/keep subset; smoothing lengths scaled by keep^(1/3) and the
+    density amplitude rho0 by keep^(1/3), so the expected emitted flux
+    (proportional to rho0 sigma^2 per particle) is preserved."""
+    import torch
+    n = int(parts["x"].numel())
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    m = max(1, n // keep)
+    idx = torch.randperm(n, generator=g)[:m].sort().values.to(parts["x"].device)
+    out = {k: t[idx].contiguous() for k, t in parts.items()}
+    k = float(keep) ** (1.0 / 3.0)
+    out["h"] = (out["h"] * k).contiguous()
+    r0 = out.get("rho0")
+    out["rho0"] = (r0 * k).contiguous() if r0 is not None else \
+        torch.full_like(out["x"], k)
+    return out
+
+
+class Reconstructor:
+    """Runs the network on a decimated render (and trains it)."""
+
+    def __init__(self, net: UNet):
+        self.net = net
+        self.ops = Ops()
+        self.sc = Scratch(net.dev)
+
+    def _scale(self, img):
+        import torch
+        part = self.sc.get("sum", 1, torch.float32)
+        self.ops.colsum(img.reshape(-1, 1), img.numel(), 1, part,
+                        self.sc.get("colsum", 1024, torch.float32))
+        s = float(part.item()) / img.numel()
+        return s if s > 0 else 1.0
+
+    def tonemap_pair(self, dec_imgs, full_imgs=None):
+        """Planar [3,H,W] images -> stacked NHWC tone maps (FP32 + BF16)."""
+        import torch
+        n = len(dec_imgs)
+        _, h, w = dec_imgs[0].shape
+        P = h * w
+        x_f = self.sc.get("x_f", n * P * CIN, torch.float32)
+        x_bf = self.sc.get("x_bf", n * P * CIN, torch.int16)
+        t_f = self.sc.get("t_f", n * P * CIN, torch.float32) if full_imgs is not None else None
+        scales = []
+        for k in range(n):
+            s = self._scale(dec_imgs[k])
+            scales.append(s)
+            self.ops.tonemap(dec_imgs[k], h, w, s, CIN, x_f[k * P * CIN:], x_bf[k * P * CIN:])
+            if full_imgs is not None:
+                self.ops.tonemap(full_imgs[k], h, w, s, CIN, t_f[k * P * CIN:], None)
+        return x_f, x_bf, t_f, scales
+
+    def train_step(self, dec_imgs, full_imgs, lr=1e-3):
+        import torch
+        n = len(dec_imgs)
+        _, h, w = dec_imgs[0].shape
+        x_f, x_bf, t_f, _ = self.tonemap_pair(dec_imgs, full_imgs)
+        y = self.net.forward(x_f, x_bf, n, h, w)
+        P = n * h * w
+        gy = self.sc.get("gy", P * CIN, torch.float32)
+        part = self.sc.get("loss", 256, torch.float32)
+        self.ops.mse(y, t_f, gy, P, CIN, 3, part, 256)
+        self.net.backward(gy)
+        self.net.adam_step(lr)
+        return part
+
+    def infer(self, dec_img):
+        """Reconstructed planar [3,H,W] image from one decimated render."""
+        import torch
+        _, h, w = dec_img.shape
+        x_f, x_bf, _, scales = self.tonemap_pair([dec_img])
+        y = self.net.forward(x_f, x_bf, 1, h, w)
+        out = torch.empty_like(dec_img)
+        self.ops.untonemap(y, h, w, scales[0], CIN, out)
+        return out
+
+
+def psnr_tonemapped(img, ref):
+    """PSNR of img against ref after the tone map T(I) = log1p(I/s) /
+    log1p(max(ref)/s), s = mean of ref (host numpy arrays [3,H,W])."""
+    ref = np.asarray(ref, np.float64)
+    img = np.asarray(img, np.float64)
+    s = ref.mean()
+    if not s > 0:
+        return float("inf")
+    den = math.log1p(ref.max() / s)
+    a = np.log1p(np.maximum(img, 0) / s) / den
+    b = np.log1p(np.maximum(ref, 0) / s) / den
+    mse = float(((a - b) ** 2).mean())
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def probe_mask(width, height, tile, frac, seed, device):
+    """Seeded random set of screen tiles (uint8 mask), about frac of them."""
+    import torch
+    ntx, nty = -(-width // tile), -(-height // tile)
+    rng = np.random.default_rng(seed)
+    m = (rng.uniform(size=ntx * nty) < frac).astype(np.uint8)
+    if not m.any():
+        m[rng.integers(0, m.size)] = 1
+    return torch.from_numpy(m).to(device), m.reshape(nty, ntx)
+
+
+def render_learned(parts_full, parts_dec, cam, palette, species, recon: Reconstructor, *,
+                   threshold_db=40.0, probe_frac=0.02, seed=0, tile=16, **kw):
+    """Decimated render + reconstruction, checked by a probe: the full set
+    rendered on a seeded sample of tiles.  Returns (image, info) where
+    info has the probe PSNR and whether the full render was used instead."""
+    import torch
+    dec = B.render(parts_dec, cam, palette, species, tile=tile, **kw)
+    rec = recon.infer(dec)
+    mask_t, mask = probe_mask(cam.width, cam.height, tile, probe_frac, seed, dec.device)
+    probe = torch.zeros_like(rec)
+    B.render(parts_full, cam, palette, species, probe, tile=tile, tile_mask=mask_t, **kw)
+    rows = np.repeat(np.repeat(mask, tile, 0), tile, 1)[:cam.height, :cam.width].astype(bool)
+    sel = torch.from_numpy(rows).to(dec.device)
+    a = rec[:, sel].cpu().numpy()
+    b = probe[:, sel].cpu().numpy()
+    p = psnr_tonemapped(a, b)
+    info = dict(probe_psnr=p, fallback=bool(p < threshold_db), probe_tiles=int(mask.sum()))
+    if info["fallback"]:
+        return B.render(parts_full, cam, palette, species, tile=tile, **kw), info
+    return rec, info

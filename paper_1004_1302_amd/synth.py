@@ -88,6 +88,25 @@ def ortho_unit_square(width=256, height=256) -> Camera:
                   px_per_unit=float(width), z_near=0.0, z_far=10.0)
 
 
+def orbit_cameras(n_views, seed, sizes, centre=(0.5, 0.5, 0.5), radius=2.0, fov_x_deg=60.0,
+                  z_near=0.05, z_far=100.0):
+    """Perspective cameras at seeded random points of a sphere of `radius`
+    around `centre`, looking at it, with resolutions drawn from `sizes`
+    (a list of (width, height))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cams = []
+    for _ in range(n_views):
+        th = math.acos(rng.uniform(-1.0, 1.0))
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        eye = np.asarray(centre, np.float64) + radius * np.array(
+            [math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        w, h = sizes[int(rng.integers(0, len(sizes)))]
+        up = (0.0, 1.0, 0.0) if abs(math.cos(th)) < 0.9 else (1.0, 0.0, 0.0)
+        cams.append(look_at(eye, centre, up, PERSPECTIVE, w, h, fov_x_deg, z_near=z_near,
+                            z_far=z_far))
+    return cams
+
+
 def palette(n_entries: int = 256) -> np.ndarray:
     """A project-defined analytic RGB ramp (black -> red -> yellow -> white,
     with a blue lift in the mid range), as ``(K, 3)`` float32."""

@@ -12,21 +12,8 @@ from paper_1004_1302_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-def orbit_cameras(n_views, seed, sizes, centre=(0.5, 0.5, 0.5), radius=2.0):
-    """Cameras on a seeded orbit around the centre, 60 degree field of view,
-    resolutions drawn from `sizes`."""
-    rng = np.random.default_rng(seed)
-    cams = []
-    for _ in range(n_views):
-        th = np.arccos(rng.uniform(-1, 1))
-        ph = rng.uniform(0, 2 * np.pi)
-        eye = np.array(centre) + radius * np.array([np.sin(th) * np.cos(ph),
-                                                    np.sin(th) * np.sin(ph), np.cos(th)])
-        w, h = sizes[rng.integers(0, len(sizes))]
-        up = (0, 1, 0) if abs(np.cos(th)) < 0.9 else (1, 0, 0)
-        cams.append(synth.look_at(eye, centre, up, synth.PERSPECTIVE, w, h, 60.0,
-                                  z_near=0.05, z_far=100.0))
-    return cams
+def orbit_cameras(n_views, seed, sizes):
+    return synth.orbit_cameras(n_views, seed, sizes)
 
 
 @pytest.fixture(scope="module")
