@@ -96,7 +96,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lognormal", choices=["lognormal", "nfw", "plummer"])
+    ap.add_argument("--workload", default="lognormal",
+                    choices=["lognormal", "nfw", "plummer", "learned"])
+    ap.add_argument("--train-pairs", type=int, default=2000)
+    ap.add_argument("--test-views", type=int, default=20)
+    ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--n", type=float, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--tile", type=int, default=16)
@@ -114,6 +118,8 @@ def main():
     from paper_1004_1302_amd import binding as B
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "learned":
+        return learned_leg(args, np, torch)
 
     t0 = time.perf_counter()
     parts, cam, sp, pal, cfg = make_workload(args, torch)
@@ -195,6 +201,90 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(parts, cam, sp, args, np, torch)
+    print(json.dumps(out), flush=True)
+
+
+def learned_leg(args, np, torch):
+    """Learned decimation against the plain render: 20M particles of the
+    Plummer-mix generator, square images of --size px from cameras on a
+    seeded orbit; the network trains on pairs the renderer makes on the fly
+    (--train-pairs views, 4 per step) and is evaluated on --test-views
+    held-out views (tone-mapped PSNR, max error), with frame times of the
+    learned path (decimated render + network + probe) and of the full
+    render."""
+    from paper_1004_1302_amd import binding as B
+    from paper_1004_1302_amd import learned as LN
+    from paper_1004_1302_amd import synth
+    n = int(args.n or 20_000_000)
+    t0 = time.perf_counter()
+    sc = synth.plummer_mix(n, seed=5)
+    parts, pal = B.scene_to_device(sc, "cuda:0")
+    dec = LN.decimate(parts, seed=6)
+    sp = sc.species_params
+    size = args.size
+    cams = synth.orbit_cameras(args.train_pairs + args.test_views, 9, [(size, size)])
+    train, test = cams[:args.train_pairs], cams[args.train_pairs:]
+    log(f"learned: {n} particles ({int(dec['x'].numel())} decimated) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    net = LN.UNet(seed=0)
+    rec = LN.Reconstructor(net)
+    kw = dict(compensated=True)
+    t1 = time.perf_counter()
+    batch = 4
+    steps = max(1, len(train) // batch)
+    for it in range(steps):
+        views = train[it * batch:(it + 1) * batch]
+        d = [B.render(dec, c, pal, sp, **kw).clone() for c in views]
+        f = [B.render(parts, c, pal, sp, **kw).clone() for c in views]
+        lr = 1e-3 if it < 0.7 * steps else 3e-4
+        part = rec.train_step(d, f, lr=lr)
+        if it % 50 == 0 or it == steps - 1:
+            loss = float(part.sum().item()) / (batch * size * size * 3)
+            log(f"train step {it + 1}/{steps} loss {loss:.3e}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    psnr_net, psnr_dec, maxerr, fb = [], [], [], 0
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    t_learn, t_full = [], []
+    for c in test:
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        full = B.render(parts, c, pal, sp, **kw)
+        e1.record()
+        img, info = LN.render_learned(parts, dec, c, pal, sp, rec, threshold_db=40.0, **kw)
+        e2.record()
+        torch.cuda.synchronize()
+        t_full.append(e0.elapsed_time(e1))
+        t_learn.append(e1.elapsed_time(e2))
+        d = B.render(dec, c, pal, sp, **kw)
+        out = rec.infer(d)
+        torch.cuda.synchronize()
+        fh, oh, dh = full.cpu().numpy(), out.cpu().numpy(), d.cpu().numpy()
+        psnr_net.append(LN.psnr_tonemapped(oh, fh))
+        psnr_dec.append(LN.psnr_tonemapped(dh, fh))
+        maxerr.append(float(np.abs(oh - fh).max() / max(np.abs(fh).max(), 1e-30)))
+        fb += int(info["fallback"])
+    med = lambda a: float(np.median(a))
+    out = {
+        "metric": METRIC,
+        "value": round(med(psnr_net), 3),
+        "unit": "dB (tone-mapped PSNR of the learned reconstruction vs the full render)",
+        "higher_is_better": True,
+        "n_gpus": 1,
+        "dtype": "bf16 network, f32 render",
+        "data": "synthetic",
+        "config": dict(workload="learned_decimation", n_particles=n, decimation=LN.DECIMATE,
+                       width=size, height=size, train_pairs=len(train), test_views=len(test),
+                       params=net.n_params(), levels=list(LN.LEVELS)),
+        "psnr_net_median_db": round(med(psnr_net), 3),
+        "psnr_decimated_median_db": round(med(psnr_dec), 3),
+        "psnr_gain_median_db": round(med(np.array(psnr_net) - np.array(psnr_dec)), 3),
+        "max_rel_error_median": round(med(maxerr), 5),
+        "fallback_rate_at_40db": fb / len(test),
+        "ms_full_render_median": round(med(t_full), 3),
+        "ms_learned_path_median": round(med(t_learn), 3),
+        "train_seconds": round(train_s, 1),
+    }
     print(json.dumps(out), flush=True)
 
 

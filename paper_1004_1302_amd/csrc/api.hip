@@ -298,7 +298,7 @@ splotch_status run_project(const Ctx &c, const splotch_particles *P, const splot
     a.o_key = o_key;
     TRY(launch_fill_u32(c.at<uint32_t>(c.L.counters), 0u, 2 * kCntN, c.s));
     uint32_t *range = c.at<uint32_t>(c.L.range);
-    TRY(launch_value_range(a, range, c.s));
+    TRY(launch_range_init(range, c.s));
     a.range_bits = range;
     TRY(launch_project(a, c.s));
     TRY(const_cast<Prof &>(c.prof).mark(0));
@@ -579,6 +579,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         sa.image = images[v].rgb;
         sa.member_count = c.at<unsigned long long>(c.L.mcount);
         sa.tile_mask = p->tile_mask;
+        sa.range_bits = c.at<uint32_t>(c.L.range);
         sa.width = cam->width;
         sa.height = cam->height;
         sa.tile = c.L.tile;
@@ -705,6 +706,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.ordered = c.L.ordered ? 1 : 0;
     sa.member_count = c.at<unsigned long long>(c.L.mcount);
     sa.tile_mask = p->tile_mask;
+    sa.range_bits = c.at<uint32_t>(c.L.range);
     sa.seg_off = c.at<uint64_t>(c.L.seg_off);
     sa.part_off = c.at<uint64_t>(c.L.part_off);
     sa.item_tile = c.at<uint32_t>(c.L.item_tile);

@@ -43,16 +43,38 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
         }
 }
 
+// Boundaries of each tile's run in the sorted pair keys.  Each thread
+// takes four consecutive keys (one 16-byte load) plus its right neighbour.
 __global__ void k_tile_ranges(const uint32_t *keys, size_t n_cap, const uint64_t *n_dev,
                               uint32_t *start, uint32_t *end, uint32_t n_tiles) {
     size_t n = n_cap;
     if (n_dev && *n_dev < n) n = (size_t)*n_dev;
+    const size_t nq = (n + 3) / 4;
     size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
-        uint32_t key = keys[p];
-        if (key >= n_tiles) continue;  // cannot happen for emitted pairs; keeps stores in bounds
-        if (p == 0 || keys[p - 1] != key) start[key] = (uint32_t)p;
-        if (p == n - 1 || keys[p + 1] != key) end[key] = (uint32_t)(p + 1);
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += stride) {
+        const size_t p0 = 4 * q;
+        uint32_t k[5];
+        if (p0 + 4 <= n) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(keys + p0);
+            k[0] = v.x;
+            k[1] = v.y;
+            k[2] = v.z;
+            k[3] = v.w;
+        } else {
+            for (int j = 0; j < 4; ++j) k[j] = p0 + j < n ? keys[p0 + j] : 0xFFFFFFFFu;
+        }
+        const uint32_t prev = p0 > 0 ? keys[p0 - 1] : 0xFFFFFFFFu;
+        k[4] = p0 + 4 < n ? keys[p0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t p = p0 + j;
+            if (p >= n) break;
+            const uint32_t key = k[j];
+            if (key >= n_tiles) continue;  // cannot happen for emitted pairs; keeps stores in bounds
+            const uint32_t before = j == 0 ? prev : k[j - 1];
+            if (p == 0 || before != key) start[key] = (uint32_t)p;
+            if (p == n - 1 || k[j + 1] != key) end[key] = (uint32_t)(p + 1);
+        }
     }
 }
 
@@ -124,7 +146,7 @@ hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs,
     if (e != hipSuccess) return e;
     e = launch_fill_u32(end, 0u, n_tiles, s);
     if (e != hipSuccess || n_pairs == 0) return e;
-    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(n_pairs, 1u << 20)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for((n_pairs + 3) / 4, 1u << 20)), dim3(kThreads), 0, s,
                        sorted_keys, n_pairs, n_pairs_dev, start, end, n_tiles);
     return hipGetLastError();
 }

@@ -35,7 +35,7 @@ struct SpeciesDev {
 //   a.x = i0 | i1 << 14 | species << 28     a.y = j0 | j1 << 14
 //   a.z = float(u - i0)                     a.w = float(v - j0)
 //   b.x = float((f sigma_s)^2)              b.y = float(log2(e) / sigma_s^2)
-//   b.z = t (normalised value)              b.w = rho0
+//   b.z = value (raw scalar)                b.w = rho0
 struct Rec {
     uint4 a, b;
 };
@@ -52,7 +52,7 @@ struct ProjectArgs {
     double soh, f;
     int tile, ntx;
     const uint8_t *tile_mask;    // per tile, 0 = skip; null = all tiles
-    const uint32_t *range_bits;  // [2*kMaxSpecies] ordered bits of auto min/max, or null
+    uint32_t *range_bits;        // [2*kMaxSpecies] ordered bits of auto min/max (atomics)
     Rec *rec;
     uint32_t *cnt;   // tile count per particle
     uint32_t *key;   // depth key per particle (kEmptyKey when not visible), may be null
@@ -67,7 +67,8 @@ struct ProjectArgs {
 // ---- launchers (one per kernel family) ------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
-hipError_t launch_value_range(const ProjectArgs &a, uint32_t *range_bits, hipStream_t s);
+// Reset the auto-range slots (min = all ones, max = 0) before the projection.
+hipError_t launch_range_init(uint32_t *range_bits, hipStream_t s);
 hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
 
 // Exclusive scan of n uint32 counts into n+1 uint64 offsets (out[n] = total).
@@ -133,6 +134,7 @@ struct SplatArgs {
     float *image;
     unsigned long long *member_count;  // [2 per tile]: all, absorbing; summed over chunks
     const uint8_t *tile_mask;          // per tile, 0 = leave untouched; null = all tiles
+    const uint32_t *range_bits;        // auto value ranges found by the projection
     int width, height, tile, ntx, nty;
     int accumulate, compensated, ordered;
 };
@@ -159,5 +161,51 @@ uint32_t splat_grid(uint32_t n_tiles, uint64_t npairs, uint32_t seg_len);
 hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Monotone unsigned image of a binary32 value, and its inverse.
+__host__ __device__ inline uint32_t order_bits_u(uint32_t b) {
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ inline uint32_t from_order_bits_u(uint32_t k) {
+    return (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+}
+
+// Normalised scalar t in [0, 1] (Section 3.2: values are normalised before
+// colouring): (g(v) - g(vmin)) / (g(vmax) - g(vmin)) clamped, g = log10 or
+// the identity; t = 0 for non-positive values under log10 or an empty range.
+__device__ __forceinline__ float normalise_value(float v, float vmin, float vmax, int log_scale) {
+    float gv, g0, g1;
+    if (log_scale) {
+        if (!(v > 0.0f) || !(vmin > 0.0f) || !(vmax > 0.0f)) return 0.0f;
+        gv = log10f(v);
+        g0 = log10f(vmin);
+        g1 = log10f(vmax);
+    } else {
+        gv = v;
+        g0 = vmin;
+        g1 = vmax;
+    }
+    float den = g1 - g0;
+    if (!(den > 0.0f)) return 0.0f;
+    float t = (gv - g0) / den;
+    return fminf(fmaxf(t, 0.0f), 1.0f);
+}
+
+// Value range of species s as used for colouring: the given one, or the
+// device min/max of the species' valid values (0, 0 when it has none).
+__device__ __forceinline__ void species_range(const SpeciesDev &sp, const uint32_t *range_bits,
+                                              int s, float *lo, float *hi) {
+    *lo = sp.vmin[s];
+    *hi = sp.vmax[s];
+    if (s < sp.n && sp.auto_range[s] && range_bits) {
+        const uint32_t bl = range_bits[2 * s], bh = range_bits[2 * s + 1];
+        if (bl == 0xFFFFFFFFu) {
+            *lo = *hi = 0.0f;
+        } else {
+            *lo = __uint_as_float(from_order_bits_u(bl));
+            *hi = __uint_as_float(from_order_bits_u(bh));
+        }
+    }
+}
 
 }  // namespace splotch

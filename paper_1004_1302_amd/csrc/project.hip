@@ -102,25 +102,6 @@ __device__ __forceinline__ bool particle_valid(float x, float y, float z, float 
            h > 0.0f && sp < ns && finite_f(r0) && r0 >= 0.0f;
 }
 
-// Normalised scalar t in [0, 1] (binary32).
-__device__ __forceinline__ float normalise(float v, float vmin, float vmax, int log_scale) {
-    float gv, g0, g1;
-    if (log_scale) {
-        if (!(v > 0.0f) || !(vmin > 0.0f) || !(vmax > 0.0f)) return 0.0f;
-        gv = log10f(v);
-        g0 = log10f(vmin);
-        g1 = log10f(vmax);
-    } else {
-        gv = v;
-        g0 = vmin;
-        g1 = vmax;
-    }
-    float den = g1 - g0;
-    if (!(den > 0.0f)) return 0.0f;
-    float t = (gv - g0) / den;
-    return fminf(fmaxf(t, 0.0f), 1.0f);
-}
-
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -142,11 +123,14 @@ __global__ void k_init_range(uint32_t *range_bits) {
     if (t < 2 * kMaxSpecies) range_bits[t] = (t & 1) ? 0u : 0xFFFFFFFFu;
 }
 
-// Exact per-species min/max of valid values (order-free: min and max of
-// binary32 values through their monotone unsigned images).
-__global__ __launch_bounds__(kThreads) void k_value_range(ProjectArgs a, uint32_t *range_bits) {
+// The projection also finds the exact per-species min/max of valid values
+// for auto ranges (order-free: min and max of binary32 values through their
+// monotone unsigned images); the colour is normalised later, when the splat
+// stages each record.
+__global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
+    __shared__ unsigned s_cnt[kCntN];
     __shared__ uint32_t s_lo[kMaxSpecies], s_hi[kMaxSpecies];
-    const int ns = a.sp.n;
+    if (threadIdx.x < kCntN) s_cnt[threadIdx.x] = 0;
     if (threadIdx.x < kMaxSpecies) {
         s_lo[threadIdx.x] = 0xFFFFFFFFu;
         s_hi[threadIdx.x] = 0u;
@@ -154,64 +138,10 @@ __global__ __launch_bounds__(kThreads) void k_value_range(ProjectArgs a, uint32_
     __syncthreads();
     uint32_t lo[kMaxSpecies], hi[kMaxSpecies];
 #pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) {
-        lo[s] = 0xFFFFFFFFu;
-        hi[s] = 0u;
+    for (int q = 0; q < kMaxSpecies; ++q) {
+        lo[q] = 0xFFFFFFFFu;
+        hi[q] = 0u;
     }
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < (size_t)a.n; k += stride) {
-        int sp = a.species ? (int)a.species[k] : 0;
-        float v = a.value[k];
-        float r0 = a.rho0 ? a.rho0[k] : 1.0f;
-        if (!particle_valid(a.x[k], a.y[k], a.z[k], a.h[k], v, r0, sp, ns)) continue;
-        if (!a.sp.auto_range[sp]) continue;
-        if (a.sp.log_scale[sp] && !(v > 0.0f)) continue;
-        uint32_t ob = order_bits(v);
-#pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s)
-            if (s == sp) {
-                lo[s] = min(lo[s], ob);
-                hi[s] = max(hi[s], ob);
-            }
-    }
-    for (int s = 0; s < ns; ++s) {
-        uint32_t l = lo[s], h = hi[s];
-        for (int o = 32; o > 0; o >>= 1) {
-            l = min(l, (uint32_t)__shfl_xor((int)l, o, 64));
-            h = max(h, (uint32_t)__shfl_xor((int)h, o, 64));
-        }
-        if ((threadIdx.x & 63) == 0 && l != 0xFFFFFFFFu) {
-            atomicMin(&s_lo[s], l);
-            atomicMax(&s_hi[s], h);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < ns && s_lo[threadIdx.x] != 0xFFFFFFFFu) {
-        atomicMin(&range_bits[2 * threadIdx.x], s_lo[threadIdx.x]);
-        atomicMax(&range_bits[2 * threadIdx.x + 1], s_hi[threadIdx.x]);
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
-    __shared__ unsigned s_cnt[kCntN];
-    if (threadIdx.x < kCntN) s_cnt[threadIdx.x] = 0;
-    __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
-    if (threadIdx.x < kMaxSpecies) {
-        int s = threadIdx.x;
-        float lo = a.sp.vmin[s], hi = a.sp.vmax[s];
-        if (s < a.sp.n && a.sp.auto_range[s] && a.range_bits) {
-            uint32_t bl = a.range_bits[2 * s], bh = a.range_bits[2 * s + 1];
-            if (bl == 0xFFFFFFFFu) {
-                lo = hi = 0.0f;  // no valid value in this species
-            } else {
-                lo = from_order_bits(bl);
-                hi = from_order_bits(bh);
-            }
-        }
-        s_vmin[s] = lo;
-        s_vmax[s] = hi;
-    }
-    __syncthreads();
     unsigned my[kCntN] = {0, 0, 0, 0};
     const int T = a.tile;
     size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -220,7 +150,17 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
         int sp = a.species ? (int)a.species[k] : 0;
         float r0 = a.rho0 ? a.rho0[k] : 1.0f;
         Proj p;
-        if (!particle_valid(x, y, z, h, v, r0, sp, a.sp.n)) {
+        const bool valid = particle_valid(x, y, z, h, v, r0, sp, a.sp.n);
+        if (valid && a.sp.auto_range[sp] && (!a.sp.log_scale[sp] || v > 0.0f)) {
+            const uint32_t ob = order_bits(v);
+#pragma unroll
+            for (int q = 0; q < kMaxSpecies; ++q)
+                if (q == sp) {
+                    lo[q] = min(lo[q], ob);
+                    hi[q] = max(hi[q], ob);
+                }
+        }
+        if (!valid) {
             p.status = kInvalid;
             p.i0 = p.i1 = p.j0 = p.j1 = 0;
             p.ur = p.vr = p.r2 = 0.0f;
@@ -231,7 +171,6 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
         }
         uint32_t cnt = 0, key = kEmptyKey;
         if (p.status == kVisible) {
-            float t = normalise(v, s_vmin[sp], s_vmax[sp], a.sp.log_scale[sp]);
             double qs = 1.4426950408889634 / (p.sig * p.sig);
             float qsf = (float)fmin(qs, (double)FLT_MAX);
             Rec r;
@@ -241,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
             r.a.w = __float_as_uint(p.vr);
             r.b.x = __float_as_uint(p.r2);
             r.b.y = __float_as_uint(qsf);
-            r.b.z = __float_as_uint(t);
+            r.b.z = __float_as_uint(v);
             r.b.w = __float_as_uint(r0);
             a.rec[k] = r;
             if (!a.tile_mask) {
@@ -273,9 +212,24 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
         unsigned w = wave_sum(my[c]);
         if ((threadIdx.x & 63) == 0 && w) atomicAdd(&s_cnt[c], w);
     }
+    for (int q = 0; q < a.sp.n; ++q) {
+        uint32_t l = lo[q], h = hi[q];
+        for (int o = 32; o > 0; o >>= 1) {
+            l = min(l, (uint32_t)__shfl_xor((int)l, o, 64));
+            h = max(h, (uint32_t)__shfl_xor((int)h, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0 && l != 0xFFFFFFFFu) {
+            atomicMin(&s_lo[q], l);
+            atomicMax(&s_hi[q], h);
+        }
+    }
     __syncthreads();
     if (threadIdx.x < kCntN && s_cnt[threadIdx.x])
         atomicAdd(&a.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
+    if (threadIdx.x < a.sp.n && s_lo[threadIdx.x] != 0xFFFFFFFFu) {
+        atomicMin(&a.range_bits[2 * threadIdx.x], s_lo[threadIdx.x]);
+        atomicMax(&a.range_bits[2 * threadIdx.x + 1], s_hi[threadIdx.x]);
+    }
 }
 
 unsigned grid_for(size_t n, unsigned cap) {
@@ -299,12 +253,8 @@ hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_value_range(const ProjectArgs &a, uint32_t *range_bits, hipStream_t s) {
+hipError_t launch_range_init(uint32_t *range_bits, hipStream_t s) {
     hipLaunchKernelGGL(k_init_range, dim3(1), dim3(2 * kMaxSpecies), 0, s, range_bits);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || a.n == 0) return e;
-    hipLaunchKernelGGL(k_value_range, dim3(grid_for((size_t)a.n, 4096)), dim3(kThreads), 0, s,
-                       a, range_bits);
     return hipGetLastError();
 }
 

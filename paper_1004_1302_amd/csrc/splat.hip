@@ -125,6 +125,9 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     const uint32_t tend = a.tile_end[tile];
     const uint32_t start = a.tile_start[tile] + seg * seg_len;
     const uint32_t end = (tend - start) > seg_len ? start + seg_len : tend;
+    __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
+    if (tid < kMaxSpecies) species_range(a.sp, a.range_bits, tid, &s_vmin[tid], &s_vmax[tid]);
+    __syncthreads();
 
     uint32_t n_member = 0, n_absorb = 0;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -139,7 +142,8 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                 const uint32_t idx = a.pair_val[kk2];
                 const uint4 ra = a.rec[idx].a, rb = a.rec[idx].b;
                 const int sp = (int)(ra.x >> 28);
-                const float t = __uint_as_float(rb.z);
+                const float t = normalise_value(__uint_as_float(rb.z), s_vmin[sp], s_vmax[sp],
+                                                a.sp.log_scale[sp]);
                 const float rho0 = __uint_as_float(rb.w);
                 const float pp = t * (float)(a.n_pal - 1);
                 int kk = (int)floorf(pp);
