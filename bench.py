@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--n", type=float, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--splat-variant", type=int, default=0)
     ap.add_argument("--max-pairs", type=float, default=0)
     ap.add_argument("--cpu-sample", type=float, default=2_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -129,7 +130,8 @@ def main():
     W, H = cam.width, cam.height
     image = torch.empty((3, H, W), dtype=torch.float32, device="cuda:0")
     max_pairs = int(args.max_pairs) if args.max_pairs else 4 * n + 65536
-    kw = dict(compensated=True, tile=args.tile, max_pairs=max_pairs)
+    kw = dict(compensated=True, tile=args.tile, max_pairs=max_pairs,
+              splat_variant=args.splat_variant)
 
     def step(profile=False):
         return B.render(parts, cam, pal, sp, image, profile=profile, **kw)
@@ -193,7 +195,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict(cfg, n_particles=n, tile=args.tile, pairs=pairs,
+        "config": dict(cfg, n_particles=n, tile=args.tile, splat_variant=args.splat_variant,
+                       pairs=pairs,
                        chunks=st["n_chunks"], visible=st["n_visible"]),
         "stages_ms": {k: round(v, 3) for k, v in stages.items()},
         "roofline": roof,

@@ -151,6 +151,11 @@ typedef struct splotch_params {
     int32_t seg_records; /* least records per tile-list segment (one workgroup
                             each); 0 = 1024.  Long lists are cut into segments
                             merged front to back; this only affects speed. */
+    int32_t splat_variant; /* how a workgroup walks a tile's list: 0 or 1 =
+                            every wave tests each record against its pixel
+                            rows (default); 2 = each lane first lists its
+                            member records, then composites them.  Speed
+                            only; the autotuner can choose. */
     const uint8_t *tile_mask; /* device, one byte per screen tile (row-major,
                             tiles of params->tile px), or NULL = all tiles.
                             Tiles whose byte is 0 are skipped: no pairs, no

@@ -75,7 +75,7 @@ class Params(C.Structure):
                 ("sigma_over_h", C.c_float), ("trunc_f", C.c_float),
                 ("accumulate", C.c_int32), ("compensated", C.c_int32), ("tile", C.c_int32),
                 ("profile", C.c_int32), ("seg_records", C.c_int32),
-                ("tile_mask", C.c_void_p),
+                ("splat_variant", C.c_int32), ("tile_mask", C.c_void_p),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats))]
 
@@ -174,7 +174,8 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 
 
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
-                  tile=0, profile=False, seg_records=0, tile_mask=None) -> Params:
+                  tile=0, profile=False, seg_records=0, tile_mask=None,
+                  splat_variant=0) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
@@ -190,6 +191,7 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.profile = 1 if profile else 0
     p.seg_records = int(seg_records)
     p.tile_mask = None if tile_mask is None else C.c_void_p(tile_mask.data_ptr())
+    p.splat_variant = int(splat_variant)
     return p
 
 
@@ -270,7 +272,7 @@ def _setup(parts, cam, species, max_pairs, workspace, **kw):
 
 def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, trunc_f=2.0,
            accumulate=False, compensated=False, tile=0, max_pairs=0, workspace=None,
-           stats=False, profile=False, seg_records=0, tile_mask=None):
+           stats=False, profile=False, seg_records=0, tile_mask=None, splat_variant=0):
     """Render into image (planar float32 [3, H, W] device tensor; allocated
     if None).  Returns the image, or (image, stats dict) with stats=True
     (profile=True adds per-stage milliseconds to the stats)."""
@@ -278,7 +280,7 @@ def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, 
     P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
                              trunc_f=trunc_f, accumulate=accumulate, compensated=compensated,
                              tile=tile, profile=profile, seg_records=seg_records,
-                             tile_mask=tile_mask)
+                             tile_mask=tile_mask, splat_variant=splat_variant)
     stats = stats or profile
     if image is None:
         image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)
@@ -354,7 +356,7 @@ def _side_stream(device):
 
 def render_batch(parts: dict, cams, palette, species, images=None, *, graph=False,
                  sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False, tile=0,
-                 max_pairs=0, seg_records=0, workspace=None, stats=False):
+                 max_pairs=0, seg_records=0, workspace=None, stats=False, splat_variant=0):
     """Render several camera views of one particle set (splotch_render_batch).
     images: list of [3, H_v, W_v] float32 device tensors (allocated if None).
     graph=True captures the batch into a HIP graph on first use and replays
@@ -369,7 +371,7 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
     cs = (CameraS * nv)(*[c if isinstance(c, CameraS) else camera_struct(c) for c in cams])
     prm = params_struct(species, sigma_over_h=sigma_over_h, trunc_f=trunc_f,
                         accumulate=accumulate, compensated=compensated, tile=tile,
-                        seg_records=seg_records)
+                        seg_records=seg_records, splat_variant=splat_variant)
     T = tile or 16
     big = max(range(nv), key=lambda v: (-(-cs[v].width // T)) * (-(-cs[v].height // T)))
     if workspace is None:

@@ -137,6 +137,7 @@ struct SplatArgs {
     const uint32_t *range_bits;        // auto value ranges found by the projection
     int width, height, tile, ntx, nty;
     int accumulate, compensated, ordered;
+    int lists;  // 1: per-lane member lists (see splat.hip); 0: wave-uniform walk
 };
 // Segment length rule (shared by host and device): a multiple of the
 // staging batch nt, at least seg_min, and at least pairs / kSegTarget so

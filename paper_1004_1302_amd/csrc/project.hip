@@ -260,8 +260,9 @@ hipError_t launch_range_init(uint32_t *range_bits, hipStream_t s) {
 
 hipError_t launch_project(const ProjectArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3(grid_for((size_t)a.n, 1u << 20)), dim3(kThreads), 0, s,
-                       a);
+    // grid-stride: a bounded number of blocks keeps the per-block publication
+    // of counters and value ranges (global atomics on a few words) cheap
+    hipLaunchKernelGGL(k_project, dim3(grid_for((size_t)a.n, 16384)), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

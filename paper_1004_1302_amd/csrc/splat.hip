@@ -31,14 +31,15 @@ __device__ __forceinline__ float member_d2(int i, int i0, float ur, int j, int j
 }
 
 // phi(x) = (1 - exp(-x))/x and exp(-x) = 1 - x phi(x).  For x < 1/32,
-// phi comes from its Taylor series (truncation below 3e-10) and exp(-x)
-// from one fused multiply-add: this keeps the product of thousands of
-// transmittance factors free of the bias a transcendental's last-place
-// error would add, and avoids the cancellation in 1 - exp(-x).
+// phi comes from its Taylor series to x^3 (the first dropped term, x^4/120,
+// is below 8e-9 relative, under binary32 resolution) and exp(-x) from one
+// fused multiply-add: this keeps the product of thousands of transmittance
+// factors free of the bias a transcendental's last-place error would add,
+// and avoids the cancellation in 1 - exp(-x).
 constexpr float kSeriesMax = 0.03125f;
 
 __device__ __forceinline__ void ex_phi_small(float x, float &ex, float &ph) {
-    ph = 1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f))));
+    ph = 1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f)));
     ex = __builtin_fmaf(-x, ph, 1.0f);
 }
 
@@ -92,17 +93,24 @@ struct Batch {
     static constexpr int B = (32768 / NT) < 128 ? (32768 / NT) : 128;
 };
 
-template <int T, bool ORDERED, bool KAHAN>
+// Two strategies for walking a staged batch (chosen per launch):
+//  LISTS = false: every wave walks the batch in order; for each record whose
+//    box meets its rows, each lane tests its pixel and members composite
+//    (cheap emission-only path, but lanes outside the footprint idle);
+//  LISTS = true: phase 1 builds, per lane, the ordered list of member
+//    records in LDS; phase 2 walks the lists so every active lane composites
+//    (full lane use, at the price of per-lane LDS gathers).
+template <int T, bool ORDERED, bool KAHAN, bool LISTS>
 __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     constexpr int NT = T * T;
-    constexpr int B = Batch<T>::B;
+    constexpr int B = LISTS ? Batch<T>::B : NT;
     constexpr int ROWS = 64 / T;  // pixel rows per wave
     __shared__ uint32_t s_b0[B], s_b1[B];
     __shared__ float s_ur[B], s_vr[B], s_r2[B], s_qs[B];
     __shared__ float s_e[3][B];
     __shared__ float s_a[3][B];
     // per-lane member lists: entry m of lane l at s_list[m * NT + l]
-    __shared__ uint8_t s_list[B * NT];
+    __shared__ uint8_t s_list[LISTS ? B * NT : 4];
 
     // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD runs of
     // kRun consecutive items (neighbouring tiles share that XCD's L2) while
@@ -172,6 +180,63 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
         }
         __syncthreads();
         const int nb = (int)((end - base) < (uint32_t)B ? (end - base) : (uint32_t)B);
+        if (!LISTS) {
+            for (int r = 0; r < nb; ++r) {
+                // record fields are the same for every lane: decode and cull
+                // the footprint box in scalar registers
+                const uint32_t b0 = __builtin_amdgcn_readfirstlane(s_b0[r]);
+                const uint32_t b1 = __builtin_amdgcn_readfirstlane(s_b1[r]);
+                const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
+                const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
+                if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
+                const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
+                const bool in = (uint32_t)(i - i0) <= (uint32_t)(i1 - i0) &&
+                                (uint32_t)(j - j0) <= (uint32_t)(j1 - j0) && d2 <= s_r2[r];
+                if (!in) continue;
+                ++n_member;
+                const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[r]);  // exp(-q^2)
+                const float e0 = s_e[0][r] * w, e1 = s_e[1][r] * w, e2 = s_e[2][r] * w;
+                if (!ORDERED || (b1 >> 31)) {
+                    const float v0 = ORDERED ? T0 * e0 : e0;
+                    const float v1 = ORDERED ? T1 * e1 : e1;
+                    const float v2 = ORDERED ? T2 * e2 : e2;
+                    if (KAHAN) {
+                        kahan_add(C0, K0, v0);
+                        kahan_add(C1, K1, v1);
+                        kahan_add(C2, K2, v2);
+                    } else {
+                        C0 += v0;
+                        C1 += v1;
+                        C2 += v2;
+                    }
+                } else {
+                    ++n_absorb;
+                    const float x0 = s_a[0][r] * w, x1 = s_a[1][r] * w, x2 = s_a[2][r] * w;
+                    float ex0, ex1, ex2, ph0, ph1, ph2;
+                    if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
+                        ex_phi_small(x0, ex0, ph0);
+                        ex_phi_small(x1, ex1, ph1);
+                        ex_phi_small(x2, ex2, ph2);
+                    } else {
+                        ex_phi(x0, ex0, ph0);
+                        ex_phi(x1, ex1, ph1);
+                        ex_phi(x2, ex2, ph2);
+                    }
+                    if (KAHAN) {
+                        kahan_add(C0, K0, T0 * (e0 * ph0));
+                        kahan_add(C1, K1, T1 * (e1 * ph1));
+                        kahan_add(C2, K2, T2 * (e2 * ph2));
+                    } else {
+                        C0 += T0 * (e0 * ph0);
+                        C1 += T1 * (e1 * ph1);
+                        C2 += T2 * (e2 * ph2);
+                    }
+                    T0 *= ex0;
+                    T1 *= ex1;
+                    T2 *= ex2;
+                }
+            }
+        } else {
         // phase 1: each lane lists, in order, the staged records whose
         // footprint holds its pixel (binary32 membership of the index recipe)
         int cnt = 0;
@@ -184,7 +249,8 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
             const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
             if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
             const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
-            const bool in = i >= i0 && i <= i1 && j >= j0 && j <= j1 && d2 <= s_r2[r];
+            const bool in = (uint32_t)(i - i0) <= (uint32_t)(i1 - i0) &&
+                            (uint32_t)(j - j0) <= (uint32_t)(j1 - j0) && d2 <= s_r2[r];
             if (in) {
                 s_list[cnt * NT + tid] = (uint8_t)r;
                 ++cnt;
@@ -240,6 +306,7 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                     T2 *= ex2;
                 }
             }
+        }
         }
         __syncthreads();
     }
@@ -336,9 +403,9 @@ __global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t
     for (uint64_t k = seg_off[t]; k < seg_off[t + 1]; ++k) item_tile[k] = t;
 }
 
-template <int T, bool ORDERED, bool KAHAN>
+template <int T, bool ORDERED, bool KAHAN, bool LISTS>
 hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s, a);
+    hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN, LISTS>), dim3(grid), dim3(T * T), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_merge<T, ORDERED, KAHAN>), dim3((uint32_t)(a.ntx * a.nty)), dim3(T * T),
@@ -346,13 +413,18 @@ hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int T, bool LISTS>
+hipError_t launch_tl(const SplatArgs &a, uint32_t grid, hipStream_t s) {
+    if (a.ordered)
+        return a.compensated ? launch_tok<T, true, true, LISTS>(a, grid, s)
+                             : launch_tok<T, true, false, LISTS>(a, grid, s);
+    return a.compensated ? launch_tok<T, false, true, LISTS>(a, grid, s)
+                         : launch_tok<T, false, false, LISTS>(a, grid, s);
+}
+
 template <int T>
 hipError_t launch_t(const SplatArgs &a, uint32_t grid, hipStream_t s) {
-    if (a.ordered)
-        return a.compensated ? launch_tok<T, true, true>(a, grid, s)
-                             : launch_tok<T, true, false>(a, grid, s);
-    return a.compensated ? launch_tok<T, false, true>(a, grid, s)
-                         : launch_tok<T, false, false>(a, grid, s);
+    return a.lists ? launch_tl<T, true>(a, grid, s) : launch_tl<T, false>(a, grid, s);
 }
 
 }  // namespace

@@ -255,8 +255,11 @@ class UNet:
         self.step = 0
 
     def layers(self):
+        """Encoder levels top-down, decoder levels from the deepest up, then
+        the output convolution (the order the FP64 reference uses)."""
         out = [c for pair in self.enc for c in pair]
-        out += [c for pair in self.dec for c in pair]
+        for l in range(len(self.levels) - 2, -1, -1):
+            out += list(self.dec[l])
         return out + [self.out]
 
     def n_params(self):

@@ -171,14 +171,25 @@ def test_c1_full_additive(torch_cuda, orc, tile, compensated):
 
 
 @pytest.mark.parametrize("compensated", [False, True])
-def test_c2_small_mixed_ordered(torch_cuda, orc, compensated):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_c2_small_mixed_ordered(torch_cuda, orc, compensated, variant):
     """NFW halos, gas depth-ordered with E = A plus additive dark matter,
-    perspective, at reduced size."""
+    perspective, at reduced size; both splat strategies."""
     scene = c2_small()
     ref = orc.render(scene)
-    img, st = gpu_render(scene, compensated=compensated, stats=True)
+    img, st = gpu_render(scene, compensated=compensated, stats=True, splat_variant=variant)
     check_image(img, ref)
     assert st["ordered"] == 1
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_list_variant_additive_and_edges(torch_cuda, orc, tile):
+    scene = c1(30_000, seed=8)
+    check_image(gpu_render(scene, tile=tile, splat_variant=2), orc.render(scene))
+    scene = edge_scene()
+    iin = np.random.default_rng(4).uniform(0, 0.6, (3, 77, 101))
+    check_image(gpu_render(scene, img_in=iin, tile=tile, splat_variant=2),
+                orc.render(scene, img_in=iin))
 
 
 def test_edges_ordered_with_background(torch_cuda, orc):
