@@ -151,11 +151,16 @@ typedef struct splotch_params {
     int32_t seg_records; /* least records per tile-list segment (one workgroup
                             each); 0 = 1024.  Long lists are cut into segments
                             merged front to back; this only affects speed. */
-    int32_t splat_variant; /* how a workgroup walks a tile's list: 0 or 1 =
-                            every wave tests each record against its pixel
-                            rows (default); 2 = each lane first lists its
-                            member records, then composites them.  Speed
-                            only; the autotuner can choose. */
+    int32_t splat_variant; /* how a tile's list is walked (speed only, the
+                            image is the same):
+                            0 = default (3);
+                            1 = one lane per pixel: every wave tests each
+                                record against its pixel rows;
+                            2 = one lane per pixel: each lane first lists
+                                its member records, then composites them;
+                            3 = one wave per tile, pixel state in LDS, the
+                                lanes laid over each record's footprint box.
+                            Other values: SPLOTCH_E_INVALID_ARG. */
     const uint8_t *tile_mask; /* device, one byte per screen tile (row-major,
                             tiles of params->tile px), or NULL = all tiles.
                             Tiles whose byte is 0 are skipped: no pairs, no

@@ -155,7 +155,7 @@ splotch_status validate_params(const splotch_params *p) {
         return SPLOTCH_E_UNSUPPORTED;
     if (p->accumulate != 0 && p->accumulate != 1) return SPLOTCH_E_INVALID_ARG;
     if (p->seg_records < 0) return SPLOTCH_E_INVALID_ARG;
-    if (p->splat_variant < 0 || p->splat_variant > 2) return SPLOTCH_E_INVALID_ARG;
+    if (p->splat_variant < 0 || p->splat_variant > 3) return SPLOTCH_E_INVALID_ARG;
     for (int s = 0; s < p->n_species; ++s) {
         const splotch_species &q = p->species[s];
         if (q.mode != SPLOTCH_ADDITIVE && q.mode != SPLOTCH_ORDERED) return SPLOTCH_E_INVALID_ARG;
@@ -254,6 +254,15 @@ struct Prof {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
 };
+
+// Public splat_variant -> walking strategy (0 = the default).
+int splat_variant_of(int v) {
+    switch (v) {
+        case 1: return kSplatRows;
+        case 2: return kSplatLists;
+        default: return kSplatBox;
+    }
+}
 
 struct Ctx {
     Layout L;
@@ -589,7 +598,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         sa.accumulate = p->accumulate;
         sa.compensated = p->compensated ? 1 : 0;
         sa.ordered = c.L.ordered ? 1 : 0;
-        sa.lists = p->splat_variant == 2 ? 1 : 0;
+        sa.variant = splat_variant_of(p->splat_variant);
         const uint32_t q = 64;
         const uint32_t grid = (uint32_t)((Lv.n_tiles + kSegTarget + q - 1) / q * q);
         TRY(launch_splat(sa, grid, c.s));
@@ -706,7 +715,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.nty = c.L.nty;
     sa.compensated = p->compensated ? 1 : 0;
     sa.ordered = c.L.ordered ? 1 : 0;
-    sa.lists = p->splat_variant == 2 ? 1 : 0;
+    sa.variant = splat_variant_of(p->splat_variant);
     sa.member_count = c.at<unsigned long long>(c.L.mcount);
     sa.tile_mask = p->tile_mask;
     sa.range_bits = c.at<uint32_t>(c.L.range);

@@ -137,8 +137,10 @@ struct SplatArgs {
     const uint32_t *range_bits;        // auto value ranges found by the projection
     int width, height, tile, ntx, nty;
     int accumulate, compensated, ordered;
-    int lists;  // 1: per-lane member lists (see splat.hip); 0: wave-uniform walk
+    int variant;  // kSplatBox, kSplatRows or kSplatLists (see splat.hip)
 };
+// How a workgroup walks a tile's list.
+constexpr int kSplatBox = 0, kSplatRows = 1, kSplatLists = 2;
 // Segment length rule (shared by host and device): a multiple of the
 // staging batch nt, at least seg_min, and at least pairs / kSegTarget so
 // that a pass has at most n_tiles + kSegTarget items.

@@ -39,11 +39,13 @@ __device__ __forceinline__ float member_d2(int i, int i0, float ur, int j, int j
 constexpr float kSeriesMax = 0.03125f;
 
 __device__ __forceinline__ void ex_phi_small(float x, float &ex, float &ph) {
-    ph = 1.0f + x * (-0.5f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f)));
+    ph = __builtin_fmaf(x, __builtin_fmaf(x, __builtin_fmaf(x, -1.0f / 24.0f, 1.0f / 6.0f), -0.5f),
+                        1.0f);
     ex = __builtin_fmaf(-x, ph, 1.0f);
 }
 
 __device__ __forceinline__ void ex_phi(float x, float &ex, float &ph) {
+#pragma clang fp contract(off)
     if (x < kSeriesMax) {
         ex_phi_small(x, ex, ph);
     } else {
@@ -52,11 +54,63 @@ __device__ __forceinline__ void ex_phi(float x, float &ex, float &ph) {
     }
 }
 
-__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
-    float y = v - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
+// Compensated (Kahan) accumulation into (C, K) of a term y from which the
+// running compensation K has already been subtracted.
+__device__ __forceinline__ void kahan_step(float &C, float &K, float y) {
+#pragma clang fp contract(off)
+    const float t = C + y;
+    K = (t - C) - y;
+    C = t;
+}
+
+// Adds T v to C (T = 1 when unordered), fused, optionally compensated.
+// Every splat strategy goes through here, so a pixel's value does not
+// depend on which one ran.
+template <bool ORDERED, bool KAHAN>
+__device__ __forceinline__ void add_term(float &C, float &K, float T, float v) {
+#pragma clang fp contract(off)
+    if (KAHAN)
+        kahan_step(C, K, ORDERED ? __builtin_fmaf(T, v, -K) : v - K);
+    else
+        C = ORDERED ? __builtin_fmaf(T, v, C) : C + v;
+}
+
+// One member contribution: weight w = exp(-q^2) of the particle at this
+// pixel, emission e = E c rho0 and absorption x = A c rho0 per channel.
+// Emission-only particles (A = 0) add w e (times the transmittance when
+// ordered); absorbing ones apply the exact per-particle solution of Eq. (1).
+template <bool ORDERED, bool KAHAN>
+__device__ __forceinline__ void composite(bool emit_only, float w, float e0, float e1, float e2,
+                                          float a0, float a1, float a2, float &C0, float &C1,
+                                          float &C2, float &K0, float &K1, float &K2, float &T0,
+                                          float &T1, float &T2) {
+#pragma clang fp contract(off)
+    e0 *= w;
+    e1 *= w;
+    e2 *= w;
+    if (!ORDERED || emit_only) {
+        add_term<ORDERED, KAHAN>(C0, K0, T0, e0);
+        add_term<ORDERED, KAHAN>(C1, K1, T1, e1);
+        add_term<ORDERED, KAHAN>(C2, K2, T2, e2);
+    } else {
+        const float x0 = a0 * w, x1 = a1 * w, x2 = a2 * w;
+        float ex0, ex1, ex2, ph0, ph1, ph2;
+        if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
+            ex_phi_small(x0, ex0, ph0);
+            ex_phi_small(x1, ex1, ph1);
+            ex_phi_small(x2, ex2, ph2);
+        } else {
+            ex_phi(x0, ex0, ph0);
+            ex_phi(x1, ex1, ph1);
+            ex_phi(x2, ex2, ph2);
+        }
+        add_term<true, KAHAN>(C0, K0, T0, e0 * ph0);
+        add_term<true, KAHAN>(C1, K1, T1, e1 * ph1);
+        add_term<true, KAHAN>(C2, K2, T2, e2 * ph2);
+        T0 *= ex0;
+        T1 *= ex1;
+        T2 *= ex2;
+    }
 }
 
 constexpr uint32_t kRun = 8;  // consecutive items per XCD run
@@ -65,6 +119,7 @@ constexpr uint32_t kRun = 8;  // consecutive items per XCD run
 template <bool ORDERED>
 __device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, float C0, float C1,
                                             float C2, float T0, float T1, float T2) {
+#pragma clang fp contract(off)
     if (i >= a.width || j >= a.height) return;
     const size_t plane = (size_t)a.width * a.height;
     const size_t o = (size_t)j * a.width + i;
@@ -72,9 +127,9 @@ __device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, fl
     if (a.accumulate) {
         const float in0 = img[o], in1 = img[plane + o], in2 = img[2 * plane + o];
         if (ORDERED) {
-            C0 += T0 * in0;
-            C1 += T1 * in1;
-            C2 += T2 * in2;
+            C0 = __builtin_fmaf(T0, in0, C0);
+            C1 = __builtin_fmaf(T1, in1, C1);
+            C2 = __builtin_fmaf(T2, in2, C2);
         } else {
             C0 += in0;
             C1 += in1;
@@ -84,6 +139,50 @@ __device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, fl
     img[o] = C0;
     img[plane + o] = C1;
     img[2 * plane + o] = C2;
+}
+
+// One record as the compositing loop needs it: packed box (bit 31 of b1
+// set when the particle does not absorb), membership fields, Gaussian
+// exponent scale and the emission / absorption colours E c(t) rho0 and
+// A c(t) rho0 (Section 3.2: value -> normalised t -> palette colour).
+struct Expanded {
+    uint32_t b0, b1;
+    float ur, vr, r2, qs;
+    float e[3], ab[3];
+};
+
+__device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t idx,
+                                                  const float *vmin, const float *vmax) {
+#pragma clang fp contract(off)
+    const uint4 ra = a.rec[idx].a, rb = a.rec[idx].b;
+    const int sp = (int)(ra.x >> 28);
+    const float t = normalise_value(__uint_as_float(rb.z), vmin[sp], vmax[sp], a.sp.log_scale[sp]);
+    const float rho0 = __uint_as_float(rb.w);
+    const float pp = t * (float)(a.n_pal - 1);
+    int kk = (int)floorf(pp);
+    kk = kk > a.n_pal - 2 ? a.n_pal - 2 : kk;
+    const float w1 = pp - (float)kk, w0 = 1.0f - w1;
+    const float *c0 = a.palette + 3 * kk;
+    const float cr = c0[0] * w0 + c0[3] * w1;
+    const float cg = c0[1] * w0 + c0[4] * w1;
+    const float cb = c0[2] * w0 + c0[5] * w1;
+    const float eb = a.sp.brightness[sp] * rho0;
+    const bool ord = a.sp.ordered[sp] != 0;
+    const float ab = ord ? a.sp.absorption[sp] * rho0 : 0.0f;
+    Expanded x;
+    x.b0 = ra.x;
+    x.b1 = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? 0x80000000u : 0u);
+    x.ur = __uint_as_float(ra.z);
+    x.vr = __uint_as_float(ra.w);
+    x.r2 = __uint_as_float(rb.x);
+    x.qs = __uint_as_float(rb.y);
+    x.e[0] = eb * cr;
+    x.e[1] = eb * cg;
+    x.e[2] = eb * cb;
+    x.ab[0] = ab * cr;
+    x.ab[1] = ab * cg;
+    x.ab[2] = ab * cb;
+    return x;
 }
 
 // Records staged per batch: B indices of at most 8 bits per lane list.
@@ -147,35 +246,19 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
         for (int r = tid; r < B; r += NT) {
             const uint32_t kk2 = base + r;
             if (kk2 < end) {
-                const uint32_t idx = a.pair_val[kk2];
-                const uint4 ra = a.rec[idx].a, rb = a.rec[idx].b;
-                const int sp = (int)(ra.x >> 28);
-                const float t = normalise_value(__uint_as_float(rb.z), s_vmin[sp], s_vmax[sp],
-                                                a.sp.log_scale[sp]);
-                const float rho0 = __uint_as_float(rb.w);
-                const float pp = t * (float)(a.n_pal - 1);
-                int kk = (int)floorf(pp);
-                kk = kk > a.n_pal - 2 ? a.n_pal - 2 : kk;
-                const float w1 = pp - (float)kk, w0 = 1.0f - w1;
-                const float *c0 = a.palette + 3 * kk;
-                const float cr = c0[0] * w0 + c0[3] * w1;
-                const float cg = c0[1] * w0 + c0[4] * w1;
-                const float cb = c0[2] * w0 + c0[5] * w1;
-                const float eb = a.sp.brightness[sp] * rho0;
-                const bool ord = a.sp.ordered[sp] != 0;
-                const float ab = ord ? a.sp.absorption[sp] * rho0 : 0.0f;
-                s_b0[r] = ra.x;
-                s_b1[r] = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? 0x80000000u : 0u);
-                s_ur[r] = __uint_as_float(ra.z);
-                s_vr[r] = __uint_as_float(ra.w);
-                s_r2[r] = __uint_as_float(rb.x);
-                s_qs[r] = __uint_as_float(rb.y);
-                s_e[0][r] = eb * cr;
-                s_e[1][r] = eb * cg;
-                s_e[2][r] = eb * cb;
-                s_a[0][r] = ab * cr;
-                s_a[1][r] = ab * cg;
-                s_a[2][r] = ab * cb;
+                const Expanded x = expand_record(a, a.pair_val[kk2], s_vmin, s_vmax);
+                s_b0[r] = x.b0;
+                s_b1[r] = x.b1;
+                s_ur[r] = x.ur;
+                s_vr[r] = x.vr;
+                s_r2[r] = x.r2;
+                s_qs[r] = x.qs;
+                s_e[0][r] = x.e[0];
+                s_e[1][r] = x.e[1];
+                s_e[2][r] = x.e[2];
+                s_a[0][r] = x.ab[0];
+                s_a[1][r] = x.ab[1];
+                s_a[2][r] = x.ab[2];
             }
         }
         __syncthreads();
@@ -195,46 +278,11 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                 if (!in) continue;
                 ++n_member;
                 const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[r]);  // exp(-q^2)
-                const float e0 = s_e[0][r] * w, e1 = s_e[1][r] * w, e2 = s_e[2][r] * w;
-                if (!ORDERED || (b1 >> 31)) {
-                    const float v0 = ORDERED ? T0 * e0 : e0;
-                    const float v1 = ORDERED ? T1 * e1 : e1;
-                    const float v2 = ORDERED ? T2 * e2 : e2;
-                    if (KAHAN) {
-                        kahan_add(C0, K0, v0);
-                        kahan_add(C1, K1, v1);
-                        kahan_add(C2, K2, v2);
-                    } else {
-                        C0 += v0;
-                        C1 += v1;
-                        C2 += v2;
-                    }
-                } else {
-                    ++n_absorb;
-                    const float x0 = s_a[0][r] * w, x1 = s_a[1][r] * w, x2 = s_a[2][r] * w;
-                    float ex0, ex1, ex2, ph0, ph1, ph2;
-                    if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
-                        ex_phi_small(x0, ex0, ph0);
-                        ex_phi_small(x1, ex1, ph1);
-                        ex_phi_small(x2, ex2, ph2);
-                    } else {
-                        ex_phi(x0, ex0, ph0);
-                        ex_phi(x1, ex1, ph1);
-                        ex_phi(x2, ex2, ph2);
-                    }
-                    if (KAHAN) {
-                        kahan_add(C0, K0, T0 * (e0 * ph0));
-                        kahan_add(C1, K1, T1 * (e1 * ph1));
-                        kahan_add(C2, K2, T2 * (e2 * ph2));
-                    } else {
-                        C0 += T0 * (e0 * ph0);
-                        C1 += T1 * (e1 * ph1);
-                        C2 += T2 * (e2 * ph2);
-                    }
-                    T0 *= ex0;
-                    T1 *= ex1;
-                    T2 *= ex2;
-                }
+                const bool emit_only = (b1 >> 31) != 0;
+                if (ORDERED && !emit_only) ++n_absorb;
+                composite<ORDERED, KAHAN>(emit_only, w, s_e[0][r], s_e[1][r], s_e[2][r],
+                                          s_a[0][r], s_a[1][r], s_a[2][r], C0, C1, C2, K0, K1,
+                                          K2, T0, T1, T2);
             }
         } else {
         // phase 1: each lane lists, in order, the staged records whose
@@ -258,8 +306,6 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
         }
         // phase 2: composite each lane's list front to back; lanes work on
         // different records at once, so every active lane does useful work.
-        // Emission-only records take the same path: with A = 0 the series
-        // gives phi = 1 and exp(-x) = 1 exactly.
         for (int m = 0; __ballot(m < cnt) != 0ull; ++m) {
             if (m < cnt) {
                 const int r = s_list[m * NT + tid];
@@ -267,44 +313,13 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                 const int i0 = (int)(b0 & kBboxMask), j0 = (int)(b1 & kBboxMask);
                 const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
                 const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[r]);  // exp(-q^2)
-                const float e0 = s_e[0][r] * w, e1 = s_e[1][r] * w, e2 = s_e[2][r] * w;
                 ++n_member;
-                if (!ORDERED) {
-                    if (KAHAN) {
-                        kahan_add(C0, K0, e0);
-                        kahan_add(C1, K1, e1);
-                        kahan_add(C2, K2, e2);
-                    } else {
-                        C0 += e0;
-                        C1 += e1;
-                        C2 += e2;
-                    }
-                } else {
-                    n_absorb += (b1 >> 31) ^ 1u;
-                    const float x0 = s_a[0][r] * w, x1 = s_a[1][r] * w, x2 = s_a[2][r] * w;
-                    float ex0, ex1, ex2, ph0, ph1, ph2;
-                    if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
-                        ex_phi_small(x0, ex0, ph0);
-                        ex_phi_small(x1, ex1, ph1);
-                        ex_phi_small(x2, ex2, ph2);
-                    } else {
-                        ex_phi(x0, ex0, ph0);
-                        ex_phi(x1, ex1, ph1);
-                        ex_phi(x2, ex2, ph2);
-                    }
-                    if (KAHAN) {
-                        kahan_add(C0, K0, T0 * (e0 * ph0));
-                        kahan_add(C1, K1, T1 * (e1 * ph1));
-                        kahan_add(C2, K2, T2 * (e2 * ph2));
-                    } else {
-                        C0 += T0 * (e0 * ph0);
-                        C1 += T1 * (e1 * ph1);
-                        C2 += T2 * (e2 * ph2);
-                    }
-                    T0 *= ex0;
-                    T1 *= ex1;
-                    T2 *= ex2;
-                }
+                if (ORDERED) n_absorb += (b1 >> 31) ^ 1u;
+                // emission-only records take the absorbing branch too: with
+                // A = 0 the series gives phi = 1 and exp(-x) = 1 exactly
+                composite<ORDERED, KAHAN>(false, w, s_e[0][r], s_e[1][r], s_e[2][r], s_a[0][r],
+                                          s_a[1][r], s_a[2][r], C0, C1, C2, K0, K1, K2, T0, T1,
+                                          T2);
             }
         }
         }
@@ -347,6 +362,180 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     }
 }
 
+// Box-mapped lanes (one wave per item).  Footprints are often a few pixels
+// across, so with one lane per pixel most lanes idle on each record.  Here
+// the tile's pixel state (C, Tr and the compensation terms) lives in LDS and
+// for each record the 64 lanes are laid over the record's footprint box
+// clipped to the tile, 8, 16 or 32 columns wide, in as many passes of
+// 64 >> log2(width) rows as the box needs.  One wave walks the records in
+// list order and LDS requests of a wave complete in order, so each pixel
+// still sees its particles front to back; per pixel the arithmetic is that
+// of the other strategies.
+//
+// State index of tile pixel (x, y): y T + (x ^ swz(y)).  The XOR spreads the
+// rows a pass touches over distinct LDS banks (8- and 16-wide passes for
+// T = 16, 8- and 32-wide ones for T = 32).
+template <int T>
+__device__ __forceinline__ int state_index(int x, int y) {
+    const int sw = T == 16 ? ((y >> 1) & 1) << 3 : (T == 32 ? (y & 3) << 3 : 0);
+    return y * T + (x ^ sw);
+}
+
+template <int T, bool ORDERED, bool KAHAN>
+__global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
+    constexpr int NT = T * T;
+    constexpr int NS = ORDERED ? NT : 1;
+    constexpr int NK = KAHAN ? NT : 1;
+    __shared__ float s_C[3][NT];
+    __shared__ float s_T[3][NS];
+    __shared__ float s_K[3][NK];
+    // staged records, three 16-byte rows each: {b0, b1, ur, vr},
+    // {r2, qs, e0, e1}, {e2, a0, a1, a2}
+    __shared__ uint4 s_rec[3][64];
+    __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
+
+    const uint32_t b = blockIdx.x, k = b >> 3;
+    const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
+    const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
+    if (item >= a.seg_off[ntiles]) return;
+    const uint32_t tile = a.item_tile[item];
+    if (a.tile_mask && !a.tile_mask[tile]) return;
+    const uint32_t seg = item - (uint32_t)a.seg_off[tile];
+    const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
+    const int tx0 = (int)(tile % (uint32_t)a.ntx) * T, ty0 = (int)(tile / (uint32_t)a.ntx) * T;
+    const int lane = threadIdx.x;
+    const uint32_t seg_len = *a.seg_len;
+    const uint32_t tend = a.tile_end[tile];
+    const uint32_t start = a.tile_start[tile] + seg * seg_len;
+    const uint32_t end = (tend - start) > seg_len ? start + seg_len : tend;
+    if (lane < kMaxSpecies) species_range(a.sp, a.range_bits, lane, &s_vmin[lane], &s_vmax[lane]);
+    for (int p = lane; p < NT; p += 64) {
+        s_C[0][p] = 0.f;
+        s_C[1][p] = 0.f;
+        s_C[2][p] = 0.f;
+        if (ORDERED) {
+            s_T[0][p] = 1.f;
+            s_T[1][p] = 1.f;
+            s_T[2][p] = 1.f;
+        }
+        if (KAHAN) {
+            s_K[0][p] = 0.f;
+            s_K[1][p] = 0.f;
+            s_K[2][p] = 0.f;
+        }
+    }
+    __syncthreads();
+
+    uint32_t n_member = 0, n_absorb = 0;
+    for (uint32_t base = start; base < end; base += 64) {
+        if (base + lane < end) {
+            const Expanded x = expand_record(a, a.pair_val[base + lane], s_vmin, s_vmax);
+            s_rec[0][lane] = make_uint4(x.b0, x.b1, __float_as_uint(x.ur), __float_as_uint(x.vr));
+            s_rec[1][lane] = make_uint4(__float_as_uint(x.r2), __float_as_uint(x.qs),
+                                        __float_as_uint(x.e[0]), __float_as_uint(x.e[1]));
+            s_rec[2][lane] = make_uint4(__float_as_uint(x.e[2]), __float_as_uint(x.ab[0]),
+                                        __float_as_uint(x.ab[1]), __float_as_uint(x.ab[2]));
+        }
+        __syncthreads();
+        const int nb = (int)((end - base) < 64u ? (end - base) : 64u);
+        for (int r = 0; r < nb; ++r) {
+            const uint4 q0 = s_rec[0][r];
+            const uint32_t b0 = __builtin_amdgcn_readfirstlane(q0.x);
+            const uint32_t b1 = __builtin_amdgcn_readfirstlane(q0.y);
+            const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
+            const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
+            const int ci0 = i0 > tx0 ? i0 : tx0, ci1 = i1 < tx0 + T - 1 ? i1 : tx0 + T - 1;
+            const int cj0 = j0 > ty0 ? j0 : ty0, cj1 = j1 < ty0 + T - 1 ? j1 : ty0 + T - 1;
+            if (ci0 > ci1 || cj0 > cj1) continue;
+            const int bw = ci1 - ci0 + 1;
+            const int gs = (T == 8 || bw <= 8) ? 3 : ((T == 16 || bw <= 16) ? 4 : 5);
+            const int lx = lane & ((1 << gs) - 1), ly = lane >> gs;
+            const int i = ci0 + lx;
+            const bool col_in = lx < bw;
+            const uint4 q1 = s_rec[1][r], q2 = s_rec[2][r];
+            const float ur = __uint_as_float(q0.z), vr = __uint_as_float(q0.w);
+            const float r2 = __uint_as_float(q1.x), qs = __uint_as_float(q1.y);
+            const bool emit_only = (b1 >> 31) != 0;
+            for (int y0 = cj0; y0 <= cj1; y0 += 64 >> gs) {
+                const int j = y0 + ly;
+                if (!col_in || j > cj1) continue;
+                const float d2 = member_d2(i, i0, ur, j, j0, vr);
+                if (!(d2 <= r2)) continue;
+                ++n_member;
+                if (ORDERED && !emit_only) ++n_absorb;
+                const float w = __builtin_amdgcn_exp2f(-d2 * qs);  // exp(-q^2)
+                const int o = state_index<T>(i - tx0, j - ty0);
+                float C0 = s_C[0][o], C1 = s_C[1][o], C2 = s_C[2][o];
+                float T0 = 1.f, T1 = 1.f, T2 = 1.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
+                if (ORDERED) {
+                    T0 = s_T[0][o];
+                    T1 = s_T[1][o];
+                    T2 = s_T[2][o];
+                }
+                if (KAHAN) {
+                    K0 = s_K[0][o];
+                    K1 = s_K[1][o];
+                    K2 = s_K[2][o];
+                }
+                composite<ORDERED, KAHAN>(emit_only, w, __uint_as_float(q1.z),
+                                          __uint_as_float(q1.w), __uint_as_float(q2.x),
+                                          __uint_as_float(q2.y), __uint_as_float(q2.z),
+                                          __uint_as_float(q2.w), C0, C1, C2, K0, K1, K2, T0, T1,
+                                          T2);
+                s_C[0][o] = C0;
+                s_C[1][o] = C1;
+                s_C[2][o] = C2;
+                if (ORDERED) {
+                    s_T[0][o] = T0;
+                    s_T[1][o] = T1;
+                    s_T[2][o] = T2;
+                }
+                if (KAHAN) {
+                    s_K[0][o] = K0;
+                    s_K[1][o] = K1;
+                    s_K[2][o] = K2;
+                }
+            }
+            // the next record may map another lane onto these pixels: keep
+            // its LDS reads after these writes (a wave's LDS requests are
+            // served in order, so no wait is needed)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        __syncthreads();
+    }
+    uint32_t wsum = n_member, asum = n_absorb;
+    for (int o = 32; o > 0; o >>= 1) {
+        wsum += __shfl_xor(wsum, o, 64);
+        asum += __shfl_xor(asum, o, 64);
+    }
+    if (lane == 0) {
+        // statistics only; compositing itself uses no atomics
+        if (wsum) atomicAdd(&a.member_count[2 * tile], (unsigned long long)wsum);
+        if (asum) atomicAdd(&a.member_count[2 * tile + 1], (unsigned long long)asum);
+    }
+    for (int p = lane; p < NT; p += 64) {
+        const int x = p % T, y = p / T;
+        const int o = state_index<T>(x, y);
+        const float C0 = s_C[0][o], C1 = s_C[1][o], C2 = s_C[2][o];
+        const float T0 = ORDERED ? s_T[0][o] : 1.f, T1 = ORDERED ? s_T[1][o] : 1.f,
+                    T2 = ORDERED ? s_T[2][o] : 1.f;
+        if (nseg == 1) {
+            write_pixel<ORDERED>(a, tx0 + x, ty0 + y, C0, C1, C2, T0, T1, T2);
+        } else {
+            float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
+            slot[0 * NT + p] = C0;
+            slot[1 * NT + p] = C1;
+            slot[2 * NT + p] = C2;
+            if (ORDERED) {
+                slot[3 * NT + p] = T0;
+                slot[4 * NT + p] = T1;
+                slot[5 * NT + p] = T2;
+            }
+        }
+    }
+}
+
 // Fold the partial (C, Tr) of a multi-segment tile front to back:
 // C += Tr * C_s, Tr *= Tr_s (the associative "over"); a plain sum when
 // nothing absorbs.
@@ -364,15 +553,9 @@ __global__ __launch_bounds__(T *T) void k_merge(SplatArgs a) {
     const float *slot = a.partial + (size_t)a.part_off[tile] * 6 * NT;
     for (uint32_t s = 0; s < nseg; ++s, slot += 6 * NT) {
         const float c0 = slot[tid], c1 = slot[NT + tid], c2 = slot[2 * NT + tid];
-        if (KAHAN) {
-            kahan_add(C0, K0, ORDERED ? T0 * c0 : c0);
-            kahan_add(C1, K1, ORDERED ? T1 * c1 : c1);
-            kahan_add(C2, K2, ORDERED ? T2 * c2 : c2);
-        } else {
-            C0 += ORDERED ? T0 * c0 : c0;
-            C1 += ORDERED ? T1 * c1 : c1;
-            C2 += ORDERED ? T2 * c2 : c2;
-        }
+        add_term<ORDERED, KAHAN>(C0, K0, T0, c0);
+        add_term<ORDERED, KAHAN>(C1, K1, T1, c1);
+        add_term<ORDERED, KAHAN>(C2, K2, T2, c2);
         if (ORDERED) {
             T0 *= slot[3 * NT + tid];
             T1 *= slot[4 * NT + tid];
@@ -403,9 +586,21 @@ __global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t
     for (uint64_t k = seg_off[t]; k < seg_off[t + 1]; ++k) item_tile[k] = t;
 }
 
-template <int T, bool ORDERED, bool KAHAN, bool LISTS>
+template <int T, bool ORDERED, bool KAHAN>
 hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN, LISTS>), dim3(grid), dim3(T * T), 0, s, a);
+    switch (a.variant) {
+        case kSplatRows:
+            hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN, false>), dim3(grid), dim3(T * T), 0, s,
+                               a);
+            break;
+        case kSplatLists:
+            hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN, true>), dim3(grid), dim3(T * T), 0, s,
+                               a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_splat_box<T, ORDERED, KAHAN>), dim3(grid), dim3(64), 0, s, a);
+            break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_merge<T, ORDERED, KAHAN>), dim3((uint32_t)(a.ntx * a.nty)), dim3(T * T),
@@ -413,18 +608,13 @@ hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int T, bool LISTS>
-hipError_t launch_tl(const SplatArgs &a, uint32_t grid, hipStream_t s) {
-    if (a.ordered)
-        return a.compensated ? launch_tok<T, true, true, LISTS>(a, grid, s)
-                             : launch_tok<T, true, false, LISTS>(a, grid, s);
-    return a.compensated ? launch_tok<T, false, true, LISTS>(a, grid, s)
-                         : launch_tok<T, false, false, LISTS>(a, grid, s);
-}
-
 template <int T>
 hipError_t launch_t(const SplatArgs &a, uint32_t grid, hipStream_t s) {
-    return a.lists ? launch_tl<T, true>(a, grid, s) : launch_tl<T, false>(a, grid, s);
+    if (a.ordered)
+        return a.compensated ? launch_tok<T, true, true>(a, grid, s)
+                             : launch_tok<T, true, false>(a, grid, s);
+    return a.compensated ? launch_tok<T, false, true>(a, grid, s)
+                         : launch_tok<T, false, false>(a, grid, s);
 }
 
 }  // namespace

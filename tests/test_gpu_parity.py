@@ -171,7 +171,7 @@ def test_c1_full_additive(torch_cuda, orc, tile, compensated):
 
 
 @pytest.mark.parametrize("compensated", [False, True])
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_c2_small_mixed_ordered(torch_cuda, orc, compensated, variant):
     """NFW halos, gas depth-ordered with E = A plus additive dark matter,
     perspective, at reduced size; both splat strategies."""
@@ -190,6 +190,50 @@ def test_list_variant_additive_and_edges(torch_cuda, orc, tile):
     iin = np.random.default_rng(4).uniform(0, 0.6, (3, 77, 101))
     check_image(gpu_render(scene, img_in=iin, tile=tile, splat_variant=2),
                 orc.render(scene, img_in=iin))
+
+
+def _big_footprints(n=4000, seed=12):
+    """Footprints from one pixel to several tiles across (box widths past
+    16 and 32 px), depth-ordered, with a background."""
+    sc = c2_small(n, seed=seed, w=180, h=140)
+    sc.h = (sc.h * np.random.default_rng(seed).lognormal(2.0, 1.0, n)).astype(np.float32)
+    return sc
+
+
+def _strategy_scenes():
+    big = _big_footprints()
+    tau = c2_small(30_000, seed=10, w=160, h=120)
+    tau.species_params = [
+        synth.Species(log_scale=1, brightness=3.0, absorption=3.0, mode=synth.ORDERED),
+        synth.Species(log_scale=1, brightness=0.5, absorption=0.0, mode=synth.ADDITIVE)]
+    tau.rho0 = np.random.default_rng(1).uniform(0.1, 4.0, tau.n).astype(np.float32)
+    return {"c1": (c1(40_000, seed=6), None), "c2": (c2_small(80_000, seed=5, w=240, h=150), None),
+            "edges": (edge_scene(), np.random.default_rng(4).uniform(0, 0.6, (3, 77, 101))),
+            "big": (big, np.random.default_rng(5).uniform(0, 0.3, (3, 140, 180))),
+            "tau": (tau, None)}
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("compensated", [False, True])
+def test_box_mapped_lanes_bitwise_equal_rows(torch_cuda, orc, tile, compensated):
+    """Box-mapped lanes (variant 3) composite each pixel's particles in the
+    same order with the same arithmetic as the row walk (variant 1): the
+    images are bit-identical, also with short segments (partials merged),
+    and agree with the oracle."""
+    for name, (scene, iin) in _strategy_scenes().items():
+        for seg in (0, 256):
+            kw = dict(tile=tile, compensated=compensated, seg_records=seg)
+            rows = gpu_render(scene, img_in=iin, splat_variant=1, **kw)
+            box = gpu_render(scene, img_in=iin, splat_variant=3, **kw)
+            assert np.array_equal(rows, box), (name, seg)
+        check_image(box, orc.render(scene, img_in=iin))
+
+
+def test_box_mapped_lanes_chunked(torch_cuda, orc):
+    scene = c2_small(40_000, seed=4, w=240, h=160)
+    img, st = gpu_render(scene, max_pairs=5000, stats=True, splat_variant=3)
+    assert st["n_chunks"] > 3
+    check_image(img, orc.render(scene))
 
 
 def test_edges_ordered_with_background(torch_cuda, orc):
