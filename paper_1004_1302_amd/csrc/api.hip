@@ -76,10 +76,13 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
     L.tstart = take((size_t)L.n_tiles * 4);
     L.tend = take((size_t)L.n_tiles * 4);
     L.mcount = take((size_t)L.n_tiles * 16);
-    // segments: seg_len >= max(1024, pairs / kSegTarget) keeps the number of
-    // items <= n_tiles + kSegTarget and partial slots < 2 * kSegTarget
+    // segments: seg_len >= max(seg_min, pairs / kSegTarget) keeps the number
+    // of items <= n_tiles + kSegTarget; a tile of L > seg_len records has
+    // ceil(L / seg_len) < 2 L / seg_len segments, so the partial slots of a
+    // pass number < 2 pairs / seg_len <= 2 min(kSegTarget, cap / seg_min)
+    const uint64_t seg_min = p->seg_records > 0 ? (uint64_t)p->seg_records : kSegMin;
     L.max_items = (uint64_t)L.n_tiles + kSegTarget + 64;
-    L.max_slots = std::min<uint64_t>(2 * kSegTarget, 2 * (cap / 1024) + 2);
+    L.max_slots = std::min<uint64_t>(2 * kSegTarget, 2 * (cap / seg_min) + 2);
     L.seg_len = take(4);
     L.flags = take((size_t)SPLOTCH_MAX_VIEWS * 12);  // per view: overflow flag (u32), pairs (u64)
     L.nseg = take((size_t)L.n_tiles * 4);
@@ -408,7 +411,7 @@ splotch_status run_splat_pass(Ctx &c, SplatArgs &sa, uint64_t npairs) {
                         c.at<uint32_t>(c.L.seg_len), c.at<uint32_t>(c.L.nseg),
                         c.at<uint32_t>(c.L.nmulti), c.at<uint64_t>(c.L.seg_off),
                         c.at<uint64_t>(c.L.part_off), c.at<uint32_t>(c.L.item_tile),
-                        c.at<void>(c.L.seg_scan), c.s));
+                        c.L.max_items, c.at<void>(c.L.seg_scan), c.s));
     TRY(launch_splat(sa, splat_grid(c.L.n_tiles, npairs, seg_len), c.s));
     TRY(c.prof.mark(5));
     return SPLOTCH_OK;
@@ -571,7 +574,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
                             c.at<uint32_t>(c.L.seg_len), c.at<uint32_t>(c.L.nseg),
                             c.at<uint32_t>(c.L.nmulti), c.at<uint64_t>(c.L.seg_off),
                             c.at<uint64_t>(c.L.part_off), c.at<uint32_t>(c.L.item_tile),
-                            c.at<void>(c.L.seg_scan), c.s));
+                            c.L.max_items, c.at<void>(c.L.seg_scan), c.s));
         SplatArgs sa;
         memset(&sa, 0, sizeof sa);
         sa.rec = c.at<Rec>(c.L.rec);
@@ -582,6 +585,8 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         sa.part_off = c.at<uint64_t>(c.L.part_off);
         sa.item_tile = c.at<uint32_t>(c.L.item_tile);
         sa.partial = c.at<float>(c.L.partial);
+        sa.max_slots = c.L.max_slots;
+        sa.max_items = c.L.max_items;
         sa.seg_len = c.at<uint32_t>(c.L.seg_len);
         sa.palette = cmap->rgb;
         sa.n_pal = cmap->n_entries;
@@ -723,6 +728,8 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.part_off = c.at<uint64_t>(c.L.part_off);
     sa.item_tile = c.at<uint32_t>(c.L.item_tile);
     sa.partial = c.at<float>(c.L.partial);
+    sa.max_slots = c.L.max_slots;
+    sa.max_items = c.L.max_items;
     sa.seg_len = c.at<uint32_t>(c.L.seg_len);
     TRY(launch_fill_u32(c.at<uint32_t>(c.L.mcount), 0u, (size_t)c.L.n_tiles * 4, c.s));
 

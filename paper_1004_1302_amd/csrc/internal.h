@@ -127,6 +127,8 @@ struct SplatArgs {
     const uint64_t *part_off;   // [n_tiles + 1] first partial slot of each multi-segment tile
     const uint32_t *item_tile;  // item -> tile
     float *partial;             // [slot][6][T*T]: C0 C1 C2 Tr0 Tr1 Tr2
+    uint64_t max_slots;         // partial slots in the buffer
+    uint64_t max_items;         // entries of item_tile
     const uint32_t *seg_len;    // device: records per segment for this pass
     const float *palette;
     int n_pal;
@@ -158,7 +160,8 @@ hipError_t launch_segments(const uint32_t *tile_start, const uint32_t *tile_end,
                            uint32_t n_tiles, uint64_t npairs, const uint64_t *npairs_dev,
                            uint32_t nt, uint32_t seg_min, uint32_t *seg_len, uint32_t *nseg,
                            uint32_t *nmulti, uint64_t *seg_off, uint64_t *part_off,
-                           uint32_t *item_tile, void *scratch, hipStream_t s);
+                           uint32_t *item_tile, uint64_t max_items, void *scratch,
+                           hipStream_t s);
 // Grid size (upper bound on items) for a pass with npairs pairs.
 uint32_t splat_grid(uint32_t n_tiles, uint64_t npairs, uint32_t seg_len);
 hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s);

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     const uint32_t b = blockIdx.x, k = b >> 3;
     const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
-    if (item >= a.seg_off[ntiles]) return;
+    if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
     const uint32_t tile = a.item_tile[item];
     if (a.tile_mask && !a.tile_mask[tile]) return;
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
     }
     if (nseg == 1) {
         write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
-    } else {
+    } else if (a.part_off[tile] + seg < a.max_slots) {
         float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
         slot[0 * NT + tid] = C0;
         slot[1 * NT + tid] = C1;
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
     const uint32_t b = blockIdx.x, k = b >> 3;
     const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
-    if (item >= a.seg_off[ntiles]) return;
+    if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
     const uint32_t tile = a.item_tile[item];
     if (a.tile_mask && !a.tile_mask[tile]) return;
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
                     T2 = ORDERED ? s_T[2][o] : 1.f;
         if (nseg == 1) {
             write_pixel<ORDERED>(a, tx0 + x, ty0 + y, C0, C1, C2, T0, T1, T2);
-        } else {
+        } else if (a.part_off[tile] + seg < a.max_slots) {
             float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
             slot[0 * NT + p] = C0;
             slot[1 * NT + p] = C1;
@@ -545,6 +545,7 @@ __global__ __launch_bounds__(T *T) void k_merge(SplatArgs a) {
     const uint32_t tile = blockIdx.x;
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     if (nseg <= 1 || (a.tile_mask && !a.tile_mask[tile])) return;
+    if (a.part_off[tile] + nseg > a.max_slots) return;  // never: the slot bound holds
     const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
     const int tid = threadIdx.x;
     const int i = tx * T + (tid % T), j = ty * T + (tid / T);
@@ -580,10 +581,12 @@ __global__ void k_seg_count(const uint32_t *ts, const uint32_t *te, uint32_t n_t
     nmulti[t] = n > 1 ? n : 0u;
 }
 
-__global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t *item_tile) {
+__global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t *item_tile,
+                             uint64_t max_items) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
-    for (uint64_t k = seg_off[t]; k < seg_off[t + 1]; ++k) item_tile[k] = t;
+    const uint64_t e = seg_off[t + 1] < max_items ? seg_off[t + 1] : max_items;
+    for (uint64_t k = seg_off[t]; k < e; ++k) item_tile[k] = t;
 }
 
 template <int T, bool ORDERED, bool KAHAN>
@@ -629,7 +632,8 @@ hipError_t launch_segments(const uint32_t *tile_start, const uint32_t *tile_end,
                            uint32_t n_tiles, uint64_t npairs, const uint64_t *npairs_dev,
                            uint32_t nt, uint32_t seg_min, uint32_t *seg_len, uint32_t *nseg,
                            uint32_t *nmulti, uint64_t *seg_off, uint64_t *part_off,
-                           uint32_t *item_tile, void *scratch, hipStream_t s) {
+                           uint32_t *item_tile, uint64_t max_items, void *scratch,
+                           hipStream_t s) {
     const uint32_t g = (n_tiles + 255) / 256;
     hipLaunchKernelGGL(k_seg_count, dim3(g), dim3(256), 0, s, tile_start, tile_end, n_tiles,
                        npairs, npairs_dev, nt, seg_min, seg_len, nseg, nmulti);
@@ -637,7 +641,8 @@ hipError_t launch_segments(const uint32_t *tile_start, const uint32_t *tile_end,
     if (e != hipSuccess) return e;
     if ((e = launch_scan_u32_u64(nseg, seg_off, n_tiles, scratch, s)) != hipSuccess) return e;
     if ((e = launch_scan_u32_u64(nmulti, part_off, n_tiles, scratch, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_item_tiles, dim3(g), dim3(256), 0, s, seg_off, n_tiles, item_tile);
+    hipLaunchKernelGGL(k_item_tiles, dim3(g), dim3(256), 0, s, seg_off, n_tiles, item_tile,
+                       max_items);
     return hipGetLastError();
 }
 

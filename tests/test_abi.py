@@ -75,6 +75,34 @@ def test_workspace_size_monotone():
     assert _ws_size(-1, cam, prm)[0] == 1
 
 
+def _seg_len_rule(npairs, nt, seg_min, target=8192):
+    s = max(-(-npairs // target), seg_min)
+    return -(-s // nt) * nt
+
+
+def test_segment_slot_bound():
+    """A tile of L > s records is cut into ceil(L/s) < 2L/s segments, so a
+    pass with P pairs fills fewer than 2P/s partial slots; with s at least
+    the segment minimum and at least P/8192, that is at most
+    2 min(8192, P/seg_min).  Checked on skewed tile-length mixes, and the
+    workspace grows when a shorter segment minimum needs more slots."""
+    rng = np.random.default_rng(0)
+    for trial in range(3000):
+        seg_min = int(rng.choice([1, 7, 64, 256, 300, 1024, 5000]))
+        nt = int(rng.choice([64, 256, 1024]))
+        L = (rng.pareto(0.8, int(rng.integers(1, 3000))) * seg_min).astype(np.int64)
+        if trial % 3 == 0:
+            L[:] = max(seg_min, nt) + 1
+        P = int(L.sum())
+        s = _seg_len_rule(P, nt, seg_min)
+        nseg = np.where(L == 0, 1, -(-L // s))
+        assert nseg[nseg > 1].sum() <= min(2 * 8192, 2 * (P // seg_min) + 2)
+        assert nseg.sum() <= L.size + 8192
+    cam = B.camera_struct(synth.ortho_unit_square(256, 256))
+    short, default = _params(seg_records=256), _params()
+    assert _ws_size(1000, cam, short, 10 ** 6)[1] > _ws_size(1000, cam, default, 10 ** 6)[1]
+
+
 @pytest.mark.parametrize("field,value,code", [
     ("width", 0, 1), ("height", -3, 1), ("width", 20000, 1), ("projection", 7, 1),
     ("px_per_unit", 0.0, 1), ("z_far", -5.0, 1),
