@@ -71,7 +71,7 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
     L.scan = take(scan_u32_u64_scratch_bytes(N));
     L.radix = take(radix_scratch_bytes(std::max<size_t>(L.ordered ? N : 0, (size_t)cap)));
     L.counters = take(kCntN * 8);
-    L.range = take(2 * kMaxSpecies * 4);
+    L.range = take(kRangeSlots * 4);
     L.bounds = take((2 + 2 * (kMaxChunks + 1)) * 8);
     L.tstart = take((size_t)L.n_tiles * 4);
     L.tend = take((size_t)L.n_tiles * 4);
@@ -320,7 +320,12 @@ splotch_status run_project(const Ctx &c, const splotch_particles *P, const splot
 
 // Stage 2: processing order (depth sort when ordered) and pair offsets.
 // Returns pointers to the order (or null) and the counts in that order.
-splotch_status run_order_and_scan(const Ctx &c, int64_t n, const uint32_t **order,
+// trim_keys: read the visible depth-key range back (one stream sync) and
+// sort only the digits it spans; particles outside it have no pairs, so
+// where they land does not matter.  Off where the caller cannot sync
+// (graph capture).
+splotch_status run_order_and_scan(const Ctx &c, int64_t n, bool trim_keys,
+                                  const uint32_t **order,
                                   const uint32_t **cnt_proc) {
     uint32_t *cnt = c.at<uint32_t>(c.L.cnt);
     *order = nullptr;
@@ -329,7 +334,22 @@ splotch_status run_order_and_scan(const Ctx &c, int64_t n, const uint32_t **orde
         bool in1 = false;
         uint32_t *k0 = c.at<uint32_t>(c.L.key0), *k1 = c.at<uint32_t>(c.L.key1);
         uint32_t *v0 = c.at<uint32_t>(c.L.val0), *v1 = c.at<uint32_t>(c.L.val1);
-        TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, nullptr, 32, false,
+        int bits = 32;
+        uint32_t bias = 0;
+        if (trim_keys) {
+            uint32_t kr[2];
+            TRY(hipMemcpyAsync(kr, c.at<uint32_t>(c.L.range) + 2 * kMaxSpecies, sizeof kr,
+                               hipMemcpyDeviceToHost, c.s));
+            TRY(hipStreamSynchronize(c.s));
+            if (kr[0] <= kr[1]) {
+                bias = kr[0];
+                const uint32_t span = kr[1] - kr[0];
+                bits = span == 0 ? 1 : 32 - __builtin_clz(span);
+            } else {
+                bits = 1;  // nothing visible
+            }
+        }
+        TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, nullptr, bits, bias, false,
                              c.at<void>(c.L.radix), &in1, c.s));
         const uint32_t *ord = in1 ? v1 : v0;
         // key buffers are free after the sort: counts in processing order
@@ -371,7 +391,7 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t
     int bits = 0;
     while ((1ull << bits) < (uint64_t)c.L.n_tiles) ++bits;
     bool in1 = false;
-    TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)npairs, nullptr, bits, true,
+    TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)npairs, nullptr, bits, 0u, true,
                          c.at<void>(c.L.radix), &in1, c.s));
     const uint32_t *keys = in1 ? pk1 : pk0;
     *vals = in1 ? pv1 : pv0;
@@ -539,7 +559,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         if ((st = run_project(cv, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
             return st;
         const uint32_t *order, *cnt_proc;
-        if ((st = run_order_and_scan(cv, n, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+        if ((st = run_order_and_scan(cv, n, false, &order, &cnt_proc)) != SPLOTCH_OK) return st;
         const uint64_t *total = c.at<uint64_t>(c.L.off) + n;
         EmitArgs e;
         e.rec = c.at<Rec>(c.L.rec);
@@ -564,7 +584,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         int bits = 0;
         while ((1ull << bits) < (uint64_t)Lv.n_tiles) ++bits;
         bool in1 = false;
-        TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)cap, total, bits, true,
+        TRY(radix_sort_pairs(pk0, pv0, pk1, pv1, false, (size_t)cap, total, bits, 0u, true,
                              c.at<void>(c.L.radix), &in1, c.s));
         const uint32_t *keys = in1 ? pk1 : pk0;
         const uint32_t *vals = in1 ? pv1 : pv0;
@@ -699,7 +719,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     if ((st = run_project(c, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
         return st;
     const uint32_t *order, *cnt_proc;
-    if ((st = run_order_and_scan(c, n, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+    if ((st = run_order_and_scan(c, n, true, &order, &cnt_proc)) != SPLOTCH_OK) return st;
     std::vector<uint64_t> plan;
     if ((st = plan_chunks(c, n, &plan)) != SPLOTCH_OK) return st;
     const int nch = (int)(plan.size() / 2) - 1;
@@ -784,7 +804,7 @@ splotch_status splotch_bin(const splotch_particles *P, const splotch_camera *cam
     if ((st = run_project(c, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
         return st;
     const uint32_t *order, *cnt_proc;
-    if ((st = run_order_and_scan(c, n, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+    if ((st = run_order_and_scan(c, n, true, &order, &cnt_proc)) != SPLOTCH_OK) return st;
     uint64_t total = 0;
     TRY(hipMemcpyAsync(&total, c.at<uint64_t>(c.L.off) + n, 8, hipMemcpyDeviceToHost, c.s));
     TRY(hipStreamSynchronize(c.s));

@@ -52,7 +52,8 @@ struct ProjectArgs {
     double soh, f;
     int tile, ntx;
     const uint8_t *tile_mask;    // per tile, 0 = skip; null = all tiles
-    uint32_t *range_bits;        // [2*kMaxSpecies] ordered bits of auto min/max (atomics)
+    uint32_t *range_bits;        // [2*kMaxSpecies] ordered bits of auto min/max (atomics),
+                                 // then [2]: min/max depth key of visible particles
     Rec *rec;
     uint32_t *cnt;   // tile count per particle
     uint32_t *key;   // depth key per particle (kEmptyKey when not visible), may be null
@@ -67,7 +68,9 @@ struct ProjectArgs {
 // ---- launchers (one per kernel family) ------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);
-// Reset the auto-range slots (min = all ones, max = 0) before the projection.
+// Reset the auto-range and depth-key-range slots (min = all ones, max = 0)
+// before the projection.
+constexpr int kRangeSlots = 2 * kMaxSpecies + 2;
 hipError_t launch_range_init(uint32_t *range_bits, hipStream_t s);
 hipError_t launch_project(const ProjectArgs &a, hipStream_t s);
 
@@ -79,8 +82,10 @@ hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void
 size_t scan_u32_scratch_bytes(size_t n);
 hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
-// vals_in may be null (values = 0..n-1).  With n_dev non-null the live
+// Stable LSD radix sort of (key, value) pairs on bits [0, bits) of
+// key - bias (unsigned; keys below bias or at or above bias + 2^bits are
+// placed in an unspecified order, which callers use only for entries that
+// do not matter).  vals_in may be null (values = 0..n-1).  With n_dev non-null the live
 // count is min(*n_dev, n) read on the device and n only sizes the grid
 // (graph-capturable).  Buffers k0/v0 hold the input;
 // k1/v1 are the second half of the ping-pong.  *result_in_1 tells which
@@ -89,7 +94,8 @@ hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t 
 size_t radix_scratch_bytes(size_t n);
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
-                            bool keys_needed, void *scratch, bool *result_in_1, hipStream_t s);
+                            uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
+                            hipStream_t s);
 
 // Binning.
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst,

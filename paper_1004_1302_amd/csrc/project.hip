@@ -120,7 +120,7 @@ __global__ void k_fill_f32(float *p, float v, size_t n) {
 // Min slots start at all-ones, max slots at zero.
 __global__ void k_init_range(uint32_t *range_bits) {
     int t = threadIdx.x;
-    if (t < 2 * kMaxSpecies) range_bits[t] = (t & 1) ? 0u : 0xFFFFFFFFu;
+    if (t < kRangeSlots) range_bits[t] = (t & 1) ? 0u : 0xFFFFFFFFu;
 }
 
 // The projection also finds the exact per-species min/max of valid values
@@ -129,9 +129,10 @@ __global__ void k_init_range(uint32_t *range_bits) {
 // stages each record.
 __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
     __shared__ unsigned s_cnt[kCntN];
-    __shared__ uint32_t s_lo[kMaxSpecies], s_hi[kMaxSpecies];
+    // per species value range, then the depth-key range of visible particles
+    __shared__ uint32_t s_lo[kMaxSpecies + 1], s_hi[kMaxSpecies + 1];
     if (threadIdx.x < kCntN) s_cnt[threadIdx.x] = 0;
-    if (threadIdx.x < kMaxSpecies) {
+    if (threadIdx.x <= kMaxSpecies) {
         s_lo[threadIdx.x] = 0xFFFFFFFFu;
         s_hi[threadIdx.x] = 0u;
     }
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
         lo[q] = 0xFFFFFFFFu;
         hi[q] = 0u;
     }
+    uint32_t klo = 0xFFFFFFFFu, khi = 0u;
     unsigned my[kCntN] = {0, 0, 0, 0};
     const int T = a.tile;
     size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -191,6 +193,8 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
                         cnt += a.tile_mask[ty * a.ntx + tx] ? 1u : 0u;
             }
             key = order_bits((float)p.zc);
+            klo = min(klo, key);
+            khi = max(khi, key);
         }
         a.cnt[k] = cnt;
         if (a.key) a.key[k] = key;
@@ -223,12 +227,26 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
             atomicMax(&s_hi[q], h);
         }
     }
+    if (a.key) {
+        for (int o = 32; o > 0; o >>= 1) {
+            klo = min(klo, (uint32_t)__shfl_xor((int)klo, o, 64));
+            khi = max(khi, (uint32_t)__shfl_xor((int)khi, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0 && klo != 0xFFFFFFFFu) {
+            atomicMin(&s_lo[kMaxSpecies], klo);
+            atomicMax(&s_hi[kMaxSpecies], khi);
+        }
+    }
     __syncthreads();
     if (threadIdx.x < kCntN && s_cnt[threadIdx.x])
         atomicAdd(&a.counters[threadIdx.x], (unsigned long long)s_cnt[threadIdx.x]);
     if (threadIdx.x < a.sp.n && s_lo[threadIdx.x] != 0xFFFFFFFFu) {
         atomicMin(&a.range_bits[2 * threadIdx.x], s_lo[threadIdx.x]);
         atomicMax(&a.range_bits[2 * threadIdx.x + 1], s_hi[threadIdx.x]);
+    }
+    if (threadIdx.x == 0 && s_lo[kMaxSpecies] != 0xFFFFFFFFu) {
+        atomicMin(&a.range_bits[2 * kMaxSpecies], s_lo[kMaxSpecies]);
+        atomicMax(&a.range_bits[2 * kMaxSpecies + 1], s_hi[kMaxSpecies]);
     }
 }
 
@@ -254,7 +272,7 @@ hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_range_init(uint32_t *range_bits, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_range, dim3(1), dim3(2 * kMaxSpecies), 0, s, range_bits);
+    hipLaunchKernelGGL(k_init_range, dim3(1), dim3(64), 0, s, range_bits);
     return hipGetLastError();
 }
 

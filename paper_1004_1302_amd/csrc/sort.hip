@@ -155,32 +155,36 @@ __device__ __forceinline__ size_t live_count(size_t n, const uint64_t *n_dev) {
     return d < n ? (size_t)d : n;
 }
 
+// Digit histogram of one tile.  16 copies of the counters (by lane mod 16)
+// keep a wave whose keys share a digit from serialising on one LDS address.
+constexpr int kHistCopies = 16;
+
 __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_cap,
-                                                const uint64_t *n_dev, int shift, uint32_t *hist,
-                                                uint32_t nblocks) {
+                                                const uint64_t *n_dev, int shift, uint32_t bias,
+                                                uint32_t *hist, uint32_t nblocks) {
     const size_t n = live_count(n_cap, n_dev);
-    __shared__ uint32_t sh[kW][256];
-    for (int d = threadIdx.x; d < kW * 256; d += kT) (&sh[0][0])[d] = 0;
+    __shared__ uint32_t sh[kHistCopies][256];
+    for (int d = threadIdx.x; d < kHistCopies * 256; d += kT) (&sh[0][0])[d] = 0;
     __syncthreads();
-    const int w = threadIdx.x >> 6;
+    const int c = threadIdx.x & (kHistCopies - 1);
     const size_t base = (size_t)blockIdx.x * kTile;
 #pragma unroll
     for (int q = 0; q < kIpt; ++q) {
         size_t idx = base + (size_t)q * kT + threadIdx.x;
-        if (idx < n) atomicAdd(&sh[w][(keys[idx] >> shift) & 255u], 1u);
+        if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & 255u], 1u);
     }
     __syncthreads();
     uint32_t t = 0;
 #pragma unroll
-    for (int k = 0; k < kW; ++k) t += sh[k][threadIdx.x];
+    for (int k = 0; k < kHistCopies; ++k) t += sh[k][threadIdx.x];
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
                                                    uint32_t *kout, uint32_t *vout, size_t n_cap,
                                                    const uint64_t *n_dev, int shift,
-                                                   const uint32_t *hist, uint32_t nblocks,
-                                                   int write_keys) {
+                                                   uint32_t bias, const uint32_t *hist,
+                                                   uint32_t nblocks, int write_keys) {
     const size_t n = live_count(n_cap, n_dev);
     if ((size_t)blockIdx.x * kTile >= n) return;  // whole block past the live count
     __shared__ uint32_t s_k[kTile], s_v[kTile];
@@ -189,23 +193,27 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const size_t base = (size_t)blockIdx.x * kTile;
     for (int d = tid; d < kW * 256; d += kT) (&s_wc[0][0])[d] = 0;
-    uint32_t k[kIpt], v[kIpt], r[kIpt];
+    // dg: the key's digit; entries past the live count take digit 255 so
+    // that they rank after every live entry of the tile
+    uint32_t k[kIpt], v[kIpt], r[kIpt], dg[kIpt];
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
         size_t idx = base + (size_t)w * (kIpt * 64) + (size_t)j * 64 + lane;
         if (idx < n) {
             k[j] = kin[idx];
             v[j] = vin ? vin[idx] : (uint32_t)idx;
+            dg[j] = ((k[j] - bias) >> shift) & 255u;
         } else {
             k[j] = 0xFFFFFFFFu;
             v[j] = 0u;
+            dg[j] = 255u;
         }
     }
     __syncthreads();
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
-        const uint32_t d = (k[j] >> shift) & 255u;
+        const uint32_t d = dg[j];
         uint64_t m = ~0ull;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
-        const uint32_t d = (k[j] >> shift) & 255u;
+        const uint32_t d = dg[j];
         const uint32_t pos = s_bs[d] + s_wc[w][d] + r[j];
         s_k[pos] = k[j];
         s_v[pos] = v[j];
@@ -248,7 +256,7 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
         int p = q * kT + tid;
         if (p < nvalid) {
             uint32_t key = s_k[p];
-            uint32_t d = (key >> shift) & 255u;
+            uint32_t d = ((key - bias) >> shift) & 255u;
             size_t g = (size_t)s_go[d] + (size_t)(p - (int)s_bs[d]);
             if (write_keys) kout[g] = key;
             vout[g] = s_v[p];
@@ -284,7 +292,8 @@ size_t radix_scratch_bytes(size_t n) {
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
-                            bool keys_needed, void *scratch, bool *result_in_1, hipStream_t s) {
+                            uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
+                            hipStream_t s) {
     *result_in_1 = false;
     if (n == 0) return hipSuccess;
     const uint32_t nb = (uint32_t)((n + kTile - 1) / kTile);
@@ -297,13 +306,15 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
         uint32_t *kout = src ? k0 : k1, *vout = src ? v0 : v1;
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kT), 0, s, kin, n, n_dev, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kT), 0, s, kin, n, n_dev, shift, bias, hist,
+                           nb);
         hipError_t e = launch_scan_u32(hist, (size_t)nb * 256, scan_scratch, s);
         if (e != hipSuccess) return e;
         const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kT), 0, s, kin,
                            (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin, kout,
-                           vout, n, n_dev, shift, hist, nb, (!last || keys_needed) ? 1 : 0);
+                           vout, n, n_dev, shift, bias, hist, nb,
+                           (!last || keys_needed) ? 1 : 0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         src ^= 1;

@@ -236,6 +236,41 @@ def test_box_mapped_lanes_chunked(torch_cuda, orc):
     check_image(img, orc.render(scene))
 
 
+@pytest.mark.parametrize("spread", [0.0, 1e-6, 0.25])
+def test_depth_sort_over_the_visible_key_span(torch_cuda, orc, spread):
+    """The depth sort runs only over the digits the visible depth keys span:
+    equal depths (span 0, the index decides), a span of a few ulps across a
+    power of two, and a wide one; invisible particles (behind the camera,
+    invalid) carry keys outside the span.  Pair lists are bit-exact."""
+    rng = np.random.default_rng(int(spread * 1e6) + 3)
+    n = 20_000
+    cam = synth.ortho_unit_square(96, 80)
+    z = (0.5 + spread * rng.uniform(-1, 1, n)).astype(np.float32)
+    z[:50] = -3.0                     # behind the camera: not visible
+    x = rng.uniform(0, 1, n).astype(np.float32)
+    x[50:60] = np.nan                 # invalid
+    sp = [synth.Species(log_scale=1, brightness=0.4, absorption=0.6, mode=synth.ORDERED),
+          synth.Species(brightness=0.3, mode=synth.ADDITIVE)]
+    scene = synth.Scene(x, rng.uniform(0, 1, n).astype(np.float32), z,
+                        rng.lognormal(np.log(0.02), 0.5, n).astype(np.float32),
+                        rng.lognormal(0, 1, n).astype(np.float32), cam, sp,
+                        species=rng.integers(0, 2, n).astype(np.uint8))
+    if spread == 1e-6:
+        # view depths 2 and 2 - 2^-22: keys on both sides of an exponent step
+        scene.z = np.where(np.arange(n) % 2 == 0, np.float32(1.0),
+                           np.float32(1.0 - 2.0 ** -22)).astype(np.float32)
+        scene.z[:50] = -3.0
+    parts, pal = B.scene_to_device(scene)
+    ts, te, pp, npairs = B.bin_pairs(parts, scene.camera, scene.species_params,
+                                      sigma_over_h=scene.sigma_over_h, trunc_f=scene.trunc_f,
+                                      tile=16)
+    ref = orc.project(scene, tile=16)
+    es, ee, ep = expected_bins(ref, scene, 16, True)
+    assert npairs == ep.size
+    assert np.array_equal(pp.cpu().numpy().view(np.uint32).astype(np.int64), ep)
+    check_image(gpu_render(scene), orc.render(scene))
+
+
 def test_edges_ordered_with_background(torch_cuda, orc):
     scene = edge_scene()
     iin = np.random.default_rng(3).uniform(0, 0.6, (3, 77, 101))
