@@ -153,7 +153,7 @@ typedef struct splotch_params {
                             merged front to back; this only affects speed. */
     int32_t splat_variant; /* how a tile's list is walked (speed only, the
                             image is the same):
-                            0 = default (3);
+                            0 = default (1);
                             1 = one lane per pixel: every wave tests each
                                 record against its pixel rows;
                             2 = one lane per pixel: each lane first lists

@@ -261,9 +261,9 @@ struct Prof {
 // Public splat_variant -> walking strategy (0 = the default).
 int splat_variant_of(int v) {
     switch (v) {
-        case 1: return kSplatRows;
         case 2: return kSplatLists;
-        default: return kSplatBox;
+        case 3: return kSplatBox;
+        default: return kSplatRows;
     }
 }
 
