@@ -141,8 +141,13 @@ __device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, fl
     img[2 * plane + o] = C2;
 }
 
-// One record as the compositing loop needs it: packed box (bit 31 of b1
-// set when the particle does not absorb), membership fields, Gaussian
+// Flags in the top bits of a staged record's packed row box.
+constexpr uint32_t kEmitOnly = 0x80000000u;      // A = 0: emission only
+constexpr uint32_t kEmitEqAbsorb = 0x40000000u;  // E = A per channel (same colour terms)
+constexpr uint32_t kRowMask = 0x0FFFFFFFu;       // j0 | j1 << 14
+
+// One record as the compositing loop needs it: packed box (flags above),
+// membership fields, Gaussian
 // exponent scale and the emission / absorption colours E c(t) rho0 and
 // A c(t) rho0 (Section 3.2: value -> normalised t -> palette colour).
 struct Expanded {
@@ -171,7 +176,8 @@ __device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t i
     const float ab = ord ? a.sp.absorption[sp] * rho0 : 0.0f;
     Expanded x;
     x.b0 = ra.x;
-    x.b1 = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? 0x80000000u : 0u);
+    x.b1 = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? kEmitOnly : 0u) |
+           ((ab != 0.0f && ab == eb) ? kEmitEqAbsorb : 0u);
     x.ur = __uint_as_float(ra.z);
     x.vr = __uint_as_float(ra.w);
     x.r2 = __uint_as_float(rb.x);
@@ -192,24 +198,21 @@ struct Batch {
     static constexpr int B = (32768 / NT) < 128 ? (32768 / NT) : 128;
 };
 
-// Two strategies for walking a staged batch (chosen per launch):
-//  LISTS = false: every wave walks the batch in order; for each record whose
-//    box meets its rows, each lane tests its pixel and members composite
-//    (cheap emission-only path, but lanes outside the footprint idle);
-//  LISTS = true: phase 1 builds, per lane, the ordered list of member
-//    records in LDS; phase 2 walks the lists so every active lane composites
-//    (full lane use, at the price of per-lane LDS gathers).
-template <int T, bool ORDERED, bool KAHAN, bool LISTS>
-__global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
+// Member lists (one lane per pixel, 64-pixel rows of waves): phase 1
+// builds, per lane, the ordered list of its member records in LDS; phase 2
+// walks the lists, so every active lane composites (full lane use, at the
+// price of per-lane LDS gathers).
+template <int T, bool ORDERED, bool KAHAN>
+__global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
     constexpr int NT = T * T;
-    constexpr int B = LISTS ? Batch<T>::B : NT;
+    constexpr int B = Batch<T>::B;
     constexpr int ROWS = 64 / T;  // pixel rows per wave
     __shared__ uint32_t s_b0[B], s_b1[B];
     __shared__ float s_ur[B], s_vr[B], s_r2[B], s_qs[B];
     __shared__ float s_e[3][B];
     __shared__ float s_a[3][B];
     // per-lane member lists: entry m of lane l at s_list[m * NT + l]
-    __shared__ uint8_t s_list[LISTS ? B * NT : 4];
+    __shared__ uint8_t s_list[B * NT];
 
     // Blocks are dealt to the 8 XCDs round-robin.  Give each XCD runs of
     // kRun consecutive items (neighbouring tiles share that XCD's L2) while
@@ -263,28 +266,6 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
         }
         __syncthreads();
         const int nb = (int)((end - base) < (uint32_t)B ? (end - base) : (uint32_t)B);
-        if (!LISTS) {
-            for (int r = 0; r < nb; ++r) {
-                // record fields are the same for every lane: decode and cull
-                // the footprint box in scalar registers
-                const uint32_t b0 = __builtin_amdgcn_readfirstlane(s_b0[r]);
-                const uint32_t b1 = __builtin_amdgcn_readfirstlane(s_b1[r]);
-                const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
-                const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
-                if (i1 < wx0 || i0 > wx1 || j1 < wy0 || j0 > wy1) continue;
-                const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
-                const bool in = (uint32_t)(i - i0) <= (uint32_t)(i1 - i0) &&
-                                (uint32_t)(j - j0) <= (uint32_t)(j1 - j0) && d2 <= s_r2[r];
-                if (!in) continue;
-                ++n_member;
-                const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[r]);  // exp(-q^2)
-                const bool emit_only = (b1 >> 31) != 0;
-                if (ORDERED && !emit_only) ++n_absorb;
-                composite<ORDERED, KAHAN>(emit_only, w, s_e[0][r], s_e[1][r], s_e[2][r],
-                                          s_a[0][r], s_a[1][r], s_a[2][r], C0, C1, C2, K0, K1,
-                                          K2, T0, T1, T2);
-            }
-        } else {
         // phase 1: each lane lists, in order, the staged records whose
         // footprint holds its pixel (binary32 membership of the index recipe)
         int cnt = 0;
@@ -322,7 +303,6 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
                                           T2);
             }
         }
-        }
         __syncthreads();
     }
     // per-tile count of composited (pixel, particle) contributions
@@ -358,6 +338,156 @@ __global__ __launch_bounds__(T *T) void k_splat(SplatArgs a) {
             slot[3 * NT + tid] = T0;
             slot[4 * NT + tid] = T1;
             slot[5 * NT + tid] = T2;
+        }
+    }
+}
+
+// Row walk (one lane per pixel, state in registers).  Each wave owns an
+// 8x8 block of the tile.  A batch of up to 256 records is staged in LDS,
+// 64 bytes each, read back as four broadcast 16-byte rows:
+//   {u - i0, v - j0, r^2, log2(e)/sigma^2}, {2 i0, 2 j0, 2 (i1 - i0) + 1,
+//   2 (j1 - j0) + 1} as floats, {E c rho0, flags}, {A c rho0, 0}.
+// Every wave first lists, with ballots, the staged records whose box meets
+// its block, then walks only those, in order.  Membership: with
+// a = (2 i + 1) - 2 i0 = 2 (i - i0) + 1 (exact), a in [1, 2 (i1 - i0) + 1]
+// is the box test and fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0)
+// once, which is the binary32 offset of the index recipe bit for bit.
+template <int T, bool ORDERED, bool KAHAN>
+__global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
+    constexpr int NT = T * T;
+    constexpr int NW = NT / 64;             // waves, one 8x8 block each
+    constexpr int QW = T / 8;               // blocks per tile row
+    constexpr int B = NT < 256 ? NT : 256;  // records per staged batch
+    __shared__ float4 s_r[4][B];
+    __shared__ uint32_t s_box[2][B];
+    __shared__ uint8_t s_wl[NW][B];
+    __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
+    __shared__ unsigned long long s_cnt[2][NW];
+
+    const uint32_t b = blockIdx.x, k = b >> 3;
+    const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
+    const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
+    if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
+    const uint32_t tile = a.item_tile[item];
+    if (a.tile_mask && !a.tile_mask[tile]) return;
+    const uint32_t seg = item - (uint32_t)a.seg_off[tile];
+    const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
+    const int tx0 = (int)(tile % (uint32_t)a.ntx) * T, ty0 = (int)(tile / (uint32_t)a.ntx) * T;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int bx = tx0 + (wave % QW) * 8, by = ty0 + (wave / QW) * 8;
+    const int i = bx + (lane & 7), j = by + (lane >> 3);
+    const float tfx = (float)(2 * i + 1), tfy = (float)(2 * j + 1);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t seg_len = *a.seg_len;
+    const uint32_t tend = a.tile_end[tile];
+    const uint32_t start = a.tile_start[tile] + seg * seg_len;
+    const uint32_t end = (tend - start) > seg_len ? start + seg_len : tend;
+    if (tid < kMaxSpecies) species_range(a.sp, a.range_bits, tid, &s_vmin[tid], &s_vmax[tid]);
+    __syncthreads();
+
+    uint64_t n_member = 0, n_absorb = 0;  // wave-uniform counts
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f;
+    float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
+    float T0 = 1.f, T1 = 1.f, T2 = 1.f;
+
+    for (uint32_t base = start; base < end; base += B) {
+        for (int r = tid; r < B; r += NT) {
+            if (base + r < end) {
+                const Expanded x = expand_record(a, a.pair_val[base + r], s_vmin, s_vmax);
+                const int i0 = (int)(x.b0 & kBboxMask), i1 = (int)((x.b0 >> kBboxBits) & kBboxMask);
+                const int j0 = (int)(x.b1 & kBboxMask), j1 = (int)((x.b1 >> kBboxBits) & kBboxMask);
+                s_r[0][r] = make_float4(x.ur, x.vr, x.r2, x.qs);
+                s_r[1][r] = make_float4((float)(2 * i0), (float)(2 * j0), (float)(2 * (i1 - i0) + 1),
+                                        (float)(2 * (j1 - j0) + 1));
+                s_r[2][r] = make_float4(x.e[0], x.e[1], x.e[2], __uint_as_float(x.b1 & ~kRowMask));
+                s_r[3][r] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
+                s_box[0][r] = x.b0;
+                s_box[1][r] = x.b1;
+            }
+        }
+        __syncthreads();
+        const int nb = (int)((end - base) < (uint32_t)B ? (end - base) : (uint32_t)B);
+        // this wave's list: staged records whose box meets its block, in order
+        int cnt = 0;
+        for (int c = 0; c < nb; c += 64) {
+            const int r = c + lane;
+            bool hit = false;
+            if (r < nb) {
+                const uint32_t b0 = s_box[0][r], b1 = s_box[1][r];
+                const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
+                const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
+                hit = i1 >= bx && i0 <= bx + 7 && j1 >= by && j0 <= by + 7;
+            }
+            const uint64_t m = __ballot(hit);
+            if (hit) s_wl[wave][cnt + __popcll(m & below)] = (uint8_t)r;
+            cnt += __popcll(m);
+        }
+        // the wave reads back its own list (a wave's LDS requests complete in order)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = 0; q < cnt; ++q) {
+            const int r = __builtin_amdgcn_readfirstlane((int)s_wl[wave][q]);
+            const float4 g = s_r[1][r];
+            const float4 f = s_r[0][r];
+            const float ax = tfx - g.x, ay = tfy - g.y;
+            float d2;
+            {
+#pragma clang fp contract(off)
+                const float dx = __builtin_fmaf(0.5f, ax, -f.x);
+                const float dy = __builtin_fmaf(0.5f, ay, -f.y);
+                d2 = dx * dx + dy * dy;
+            }
+            const bool in = ax >= 1.0f && ax <= g.z && ay >= 1.0f && ay <= g.w && d2 <= f.z;
+            const uint64_t mm = __ballot(in);
+            if (mm == 0ull) continue;
+            const float4 e = s_r[2][r];
+            const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
+            const bool emit_only = (flags & kEmitOnly) != 0;
+            n_member += (uint64_t)__popcll(mm);
+            if (ORDERED && !emit_only) n_absorb += (uint64_t)__popcll(mm);
+            if (!in) continue;
+            const float w = __builtin_amdgcn_exp2f(-d2 * f.w);  // exp(-q^2)
+            if (!ORDERED || emit_only) {
+                composite<ORDERED, KAHAN>(true, w, e.x, e.y, e.z, 0.f, 0.f, 0.f, C0, C1, C2, K0,
+                                          K1, K2, T0, T1, T2);
+            } else if (flags & kEmitEqAbsorb) {
+                composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, e.x, e.y, e.z, C0, C1, C2, K0,
+                                          K1, K2, T0, T1, T2);
+            } else {
+                const float4 x = s_r[3][r];
+                composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
+                                          K1, K2, T0, T1, T2);
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        s_cnt[0][wave] = n_member;
+        s_cnt[1][wave] = n_absorb;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long t = 0, ta = 0;
+        for (int w = 0; w < NW; ++w) {
+            t += s_cnt[0][w];
+            ta += s_cnt[1][w];
+        }
+        // statistics only; compositing itself uses no atomics
+        if (t) atomicAdd(&a.member_count[2 * tile], t);
+        if (ta) atomicAdd(&a.member_count[2 * tile + 1], ta);
+    }
+    if (nseg == 1) {
+        write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
+    } else if (a.part_off[tile] + seg < a.max_slots) {
+        const int p = (j - ty0) * T + (i - tx0);
+        float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
+        slot[0 * NT + p] = C0;
+        slot[1 * NT + p] = C1;
+        slot[2 * NT + p] = C2;
+        if (ORDERED) {
+            slot[3 * NT + p] = T0;
+            slot[4 * NT + p] = T1;
+            slot[5 * NT + p] = T2;
         }
     }
 }
@@ -593,11 +723,11 @@ template <int T, bool ORDERED, bool KAHAN>
 hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     switch (a.variant) {
         case kSplatRows:
-            hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN, false>), dim3(grid), dim3(T * T), 0, s,
+            hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
                                a);
             break;
         case kSplatLists:
-            hipLaunchKernelGGL((k_splat<T, ORDERED, KAHAN, true>), dim3(grid), dim3(T * T), 0, s,
+            hipLaunchKernelGGL((k_splat_lists<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
                                a);
             break;
         default:
