@@ -318,18 +318,21 @@ splotch_status run_project(const Ctx &c, const splotch_particles *P, const splot
     return SPLOTCH_OK;
 }
 
-// Stage 2: processing order (depth sort when ordered) and pair offsets.
-// Returns pointers to the order (or null) and the counts in that order.
+// Stage 2: processing order (depth sort when ordered) and pair offsets
+// (L.off, in processing order).  Returns the order (or null = particle
+// order) and the mask of an order entry's index bits: up to 2^30 particles
+// the entries carry their tile counts in the top bits, which the scan
+// decodes, so no gather of counts into the sorted order is needed.
 // trim_keys: read the visible depth-key range back (one stream sync) and
 // sort only the digits it spans; particles outside it have no pairs, so
 // where they land does not matter.  Off where the caller cannot sync
 // (graph capture).
 splotch_status run_order_and_scan(const Ctx &c, int64_t n, bool trim_keys,
-                                  const uint32_t **order,
-                                  const uint32_t **cnt_proc) {
-    uint32_t *cnt = c.at<uint32_t>(c.L.cnt);
+                                  const uint32_t **order, uint32_t *idx_mask) {
+    const uint32_t *cnt = c.at<uint32_t>(c.L.cnt);
+    uint64_t *off = c.at<uint64_t>(c.L.off);
     *order = nullptr;
-    *cnt_proc = cnt;
+    *idx_mask = 0xFFFFFFFFu;
     if (c.L.ordered && n > 0) {
         bool in1 = false;
         uint32_t *k0 = c.at<uint32_t>(c.L.key0), *k1 = c.at<uint32_t>(c.L.key1);
@@ -349,24 +352,31 @@ splotch_status run_order_and_scan(const Ctx &c, int64_t n, bool trim_keys,
                 bits = 1;  // nothing visible
             }
         }
+        const bool tag = (uint64_t)n <= (1ull << kTagShift);
         TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, nullptr, bits, bias, false,
-                             c.at<void>(c.L.radix), &in1, c.s));
+                             c.at<void>(c.L.radix), &in1, c.s, tag ? cnt : nullptr));
         const uint32_t *ord = in1 ? v1 : v0;
+        *order = ord;
+        if (tag) {
+            *idx_mask = kIdxMask;
+            TRY(const_cast<Prof &>(c.prof).mark(1));
+            TRY(launch_scan_tagged_counts(ord, cnt, off, (size_t)n, c.at<void>(c.L.scan), c.s));
+            TRY(const_cast<Prof &>(c.prof).mark(2));
+            return SPLOTCH_OK;
+        }
         // key buffers are free after the sort: counts in processing order
         TRY(launch_gather_u32(cnt, ord, k0, (size_t)n, c.s));
-        *order = ord;
-        *cnt_proc = k0;
+        cnt = k0;
     }
     TRY(const_cast<Prof &>(c.prof).mark(1));
-    TRY(launch_scan_u32_u64(*cnt_proc, c.at<uint64_t>(c.L.off), (size_t)n, c.at<void>(c.L.scan),
-                            c.s));
+    TRY(launch_scan_u32_u64(cnt, off, (size_t)n, c.at<void>(c.L.scan), c.s));
     TRY(const_cast<Prof &>(c.prof).mark(2));
     return SPLOTCH_OK;
 }
 
 // Bin one chunk [first, last) of processing positions: emit, sort by tile,
 // tile ranges.  Returns the sorted pair values via *vals.
-splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t *cnt_proc,
+splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, uint32_t idx_mask,
                              uint64_t first, uint64_t last, uint64_t off_first, uint64_t npairs,
                              const uint32_t **vals) {
     uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
@@ -374,7 +384,7 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, const uint32_t
     EmitArgs e;
     e.rec = c.at<Rec>(c.L.rec);
     e.order = order;
-    e.cnt = cnt_proc;
+    e.idx_mask = idx_mask;
     e.off = c.at<uint64_t>(c.L.off);
     e.first = first;
     e.last = last;
@@ -558,13 +568,14 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         // every view recomputes it from the same particles
         if ((st = run_project(cv, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
             return st;
-        const uint32_t *order, *cnt_proc;
-        if ((st = run_order_and_scan(cv, n, false, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+        const uint32_t *order;
+        uint32_t idx_mask;
+        if ((st = run_order_and_scan(cv, n, false, &order, &idx_mask)) != SPLOTCH_OK) return st;
         const uint64_t *total = c.at<uint64_t>(c.L.off) + n;
         EmitArgs e;
         e.rec = c.at<Rec>(c.L.rec);
         e.order = order;
-        e.cnt = cnt_proc;
+        e.idx_mask = idx_mask;
         e.off = c.at<uint64_t>(c.L.off);
         e.first = 0;
         e.last = (uint64_t)n;
@@ -718,8 +729,9 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     const int64_t n = P->n;
     if ((st = run_project(c, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
         return st;
-    const uint32_t *order, *cnt_proc;
-    if ((st = run_order_and_scan(c, n, true, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+    const uint32_t *order;
+    uint32_t idx_mask;
+    if ((st = run_order_and_scan(c, n, true, &order, &idx_mask)) != SPLOTCH_OK) return st;
     std::vector<uint64_t> plan;
     if ((st = plan_chunks(c, n, &plan)) != SPLOTCH_OK) return st;
     const int nch = (int)(plan.size() / 2) - 1;
@@ -769,7 +781,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
         const uint64_t first = plan[2 * k], last = plan[2 * k + 2];
         const uint64_t o0 = plan[2 * k + 1], o1 = plan[2 * k + 3];
         const uint32_t *vals;
-        if ((st = run_bin_chunk(c, order, cnt_proc, first, last, o0, o1 - o0, &vals)) !=
+        if ((st = run_bin_chunk(c, order, idx_mask, first, last, o0, o1 - o0, &vals)) !=
             SPLOTCH_OK)
             return st;
         sa.pair_val = vals;
@@ -803,8 +815,9 @@ splotch_status splotch_bin(const splotch_particles *P, const splotch_camera *cam
     const int64_t n = P->n;
     if ((st = run_project(c, P, cam, p, nullptr, nullptr, nullptr, nullptr)) != SPLOTCH_OK)
         return st;
-    const uint32_t *order, *cnt_proc;
-    if ((st = run_order_and_scan(c, n, true, &order, &cnt_proc)) != SPLOTCH_OK) return st;
+    const uint32_t *order;
+    uint32_t idx_mask;
+    if ((st = run_order_and_scan(c, n, true, &order, &idx_mask)) != SPLOTCH_OK) return st;
     uint64_t total = 0;
     TRY(hipMemcpyAsync(&total, c.at<uint64_t>(c.L.off) + n, 8, hipMemcpyDeviceToHost, c.s));
     TRY(hipStreamSynchronize(c.s));
@@ -812,7 +825,7 @@ splotch_status splotch_bin(const splotch_particles *P, const splotch_camera *cam
     if (total > c.L.pair_cap || total > (uint64_t)max_out) return SPLOTCH_E_CAPACITY;
     const uint32_t *vals = c.at<uint32_t>(c.L.pv0);
     if (total > 0) {
-        if ((st = run_bin_chunk(c, order, cnt_proc, 0, (uint64_t)n, 0, total, &vals)) !=
+        if ((st = run_bin_chunk(c, order, idx_mask, 0, (uint64_t)n, 0, total, &vals)) !=
             SPLOTCH_OK)
             return st;
     } else {

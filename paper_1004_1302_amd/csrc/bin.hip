@@ -21,14 +21,15 @@ __global__ void k_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t 
 __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     const uint64_t k = a.first + (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (k >= a.last) return;
-    const uint32_t c = a.cnt[k];
+    const uint64_t o0 = a.off[k];
+    const uint32_t c = (uint32_t)(a.off[k + 1] - o0);
     if (c == 0) return;
-    const uint32_t i = a.order ? a.order[k] : (uint32_t)k;
+    const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
     const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
     const int T = a.tile;
     const int tx0 = (int)(bb.x & kBboxMask) / T, tx1 = (int)((bb.x >> kBboxBits) & kBboxMask) / T;
     const int ty0 = (int)(bb.y & kBboxMask) / T, ty1 = (int)((bb.y >> kBboxBits) & kBboxMask) / T;
-    uint64_t o = a.off[k] - a.base;
+    uint64_t o = o0 - a.base;
     // Past the capacity (possible only where no host plan chunks the pass):
     // write the pairs that fit, so every slot below the capacity holds a
     // valid pair, and flag the pass.

@@ -92,10 +92,19 @@ hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t 
 // half holds the output.  keys_needed = false lets the last pass skip
 // writing keys.
 size_t radix_scratch_bytes(size_t n);
+// tag_counts (with vals_identity, n <= 2^30): the identity values carry the
+// element's count from tag_counts in bits 30-31 (1, 2, 4; 0 = other), so a
+// sorted order also gives the counts in that order without a gather.
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
                             uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
-                            hipStream_t s);
+                            hipStream_t s, const uint32_t *tag_counts = nullptr);
+constexpr int kTagShift = 30;
+constexpr uint32_t kIdxMask = (1u << kTagShift) - 1u;
+// Exclusive scan of the counts a tagged order carries (cnt: counts by
+// particle, read where the tag says "other") into n+1 offsets.
+hipError_t launch_scan_tagged_counts(const uint32_t *order, const uint32_t *cnt, uint64_t *out,
+                                     size_t n, void *scratch, hipStream_t s);
 
 // Binning.
 hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst,
@@ -103,7 +112,7 @@ hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t 
 struct EmitArgs {
     const Rec *rec;
     const uint32_t *order;   // processing order -> particle index (null = identity)
-    const uint32_t *cnt;     // tile count in processing order
+    uint32_t idx_mask;       // bits of an order entry that hold the index
     const uint64_t *off;     // pair offsets in processing order
     uint64_t first, last;    // processing positions [first, last)
     uint64_t base;           // off[first]

@@ -60,15 +60,30 @@ __device__ __forceinline__ T block_excl_scan(T v, T *s_w, T *total) {
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-template <typename TI, typename TO>
-__global__ __launch_bounds__(kT) void k_scan_reduce(const TI *in, size_t n, TO *partial) {
+// Scan inputs: plain values, or tile counts decoded from a tagged
+// processing order (see radix_sort_pairs).
+template <typename TI>
+struct LoadPlain {
+    const TI *p;
+    __device__ __forceinline__ TI operator()(size_t i) const { return p[i]; }
+};
+struct LoadTaggedCount {
+    const uint32_t *order, *cnt;
+    __device__ __forceinline__ uint32_t operator()(size_t i) const {
+        const uint32_t v = order[i], code = v >> kTagShift;
+        return code == 0 ? cnt[v & kIdxMask] : (code == 3 ? 4u : code);
+    }
+};
+
+template <typename L, typename TO>
+__global__ __launch_bounds__(kT) void k_scan_reduce(L in, size_t n, TO *partial) {
     __shared__ TO s_w[kW];
     const size_t base = (size_t)blockIdx.x * kTile;
     TO s = 0;
 #pragma unroll
     for (int q = 0; q < kIpt; ++q) {
         size_t idx = base + (size_t)q * kT + threadIdx.x;
-        if (idx < n) s += (TO)in[idx];
+        if (idx < n) s += (TO)in(idx);
     }
     TO tot;
     block_excl_scan<kW>(s, s_w, &tot);
@@ -90,9 +105,8 @@ __global__ __launch_bounds__(1024) void k_scan_partials(TO *partial, size_t m, T
     if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
-template <typename TI, typename TO>
-__global__ __launch_bounds__(kT) void k_scan_down(const TI *in, TO *out, size_t n,
-                                                  const TO *partial) {
+template <typename L, typename TO>
+__global__ __launch_bounds__(kT) void k_scan_down(L in, TO *out, size_t n, const TO *partial) {
     __shared__ TO s[kTile + kTile / 16];
     __shared__ TO s_w[kW];
     const size_t base = (size_t)blockIdx.x * kTile;
@@ -100,7 +114,7 @@ __global__ __launch_bounds__(kT) void k_scan_down(const TI *in, TO *out, size_t 
     for (int q = 0; q < kIpt; ++q) {
         int l = q * kT + threadIdx.x;
         size_t idx = base + l;
-        s[pad(l)] = idx < n ? (TO)in[idx] : (TO)0;
+        s[pad(l)] = idx < n ? (TO)in(idx) : (TO)0;
     }
     __syncthreads();
     TO v[kIpt];
@@ -131,19 +145,18 @@ __global__ void k_set_value(TO *p, TO v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-template <typename TI, typename TO>
-hipError_t scan_impl(const TI *in, TO *out, size_t n, TO *total_out, void *scratch,
-                     hipStream_t s) {
+template <typename L, typename TO>
+hipError_t scan_impl(L in, TO *out, size_t n, TO *total_out, void *scratch, hipStream_t s) {
     if (n == 0) {
         if (total_out) hipLaunchKernelGGL(k_set_value<TO>, dim3(1), dim3(64), 0, s, total_out, (TO)0);
         return hipGetLastError();
     }
     size_t nb = (n + kTile - 1) / kTile;
     TO *partial = reinterpret_cast<TO *>(scratch);
-    hipLaunchKernelGGL((k_scan_reduce<TI, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, n,
+    hipLaunchKernelGGL((k_scan_reduce<L, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, n,
                        partial);
     hipLaunchKernelGGL(k_scan_partials<TO>, dim3(1), dim3(1024), 0, s, partial, nb, total_out);
-    hipLaunchKernelGGL((k_scan_down<TI, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, out, n,
+    hipLaunchKernelGGL((k_scan_down<L, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, out, n,
                        partial);
     return hipGetLastError();
 }
@@ -153,6 +166,12 @@ __device__ __forceinline__ size_t live_count(size_t n, const uint64_t *n_dev) {
     if (!n_dev) return n;
     const uint64_t d = *n_dev;
     return d < n ? (size_t)d : n;
+}
+
+// Identity value with the tile count in the top bits (0 = look it up).
+__device__ __forceinline__ uint32_t tag_value(uint32_t idx, uint32_t count) {
+    const uint32_t code = count == 1 ? 1u : (count == 2 ? 2u : (count == 4 ? 3u : 0u));
+    return idx | (code << kTagShift);
 }
 
 // Digit histogram of one tile.  16 copies of the counters (by lane mod 16)
@@ -184,7 +203,8 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
                                                    uint32_t *kout, uint32_t *vout, size_t n_cap,
                                                    const uint64_t *n_dev, int shift,
                                                    uint32_t bias, const uint32_t *hist,
-                                                   uint32_t nblocks, int write_keys) {
+                                                   uint32_t nblocks, int write_keys,
+                                                   const uint32_t *tag) {
     const size_t n = live_count(n_cap, n_dev);
     if ((size_t)blockIdx.x * kTile >= n) return;  // whole block past the live count
     __shared__ uint32_t s_k[kTile], s_v[kTile];
@@ -201,7 +221,7 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
         size_t idx = base + (size_t)w * (kIpt * 64) + (size_t)j * 64 + lane;
         if (idx < n) {
             k[j] = kin[idx];
-            v[j] = vin ? vin[idx] : (uint32_t)idx;
+            v[j] = vin ? vin[idx] : (tag ? tag_value((uint32_t)idx, tag[idx]) : (uint32_t)idx);
             dg[j] = ((k[j] - bias) >> shift) & 255u;
         } else {
             k[j] = 0xFFFFFFFFu;
@@ -272,7 +292,14 @@ size_t scan_u32_u64_scratch_bytes(size_t n) {
 
 hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void *scratch,
                                hipStream_t s) {
-    return scan_impl<uint32_t, uint64_t>(in, out, n, out + n, scratch, s);
+    return scan_impl<LoadPlain<uint32_t>, uint64_t>(LoadPlain<uint32_t>{in}, out, n, out + n,
+                                                    scratch, s);
+}
+
+hipError_t launch_scan_tagged_counts(const uint32_t *order, const uint32_t *cnt, uint64_t *out,
+                                     size_t n, void *scratch, hipStream_t s) {
+    return scan_impl<LoadTaggedCount, uint64_t>(LoadTaggedCount{order, cnt}, out, n, out + n,
+                                                scratch, s);
 }
 
 size_t scan_u32_scratch_bytes(size_t n) {
@@ -280,7 +307,8 @@ size_t scan_u32_scratch_bytes(size_t n) {
 }
 
 hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t s) {
-    return scan_impl<uint32_t, uint32_t>(data, data, n, nullptr, scratch, s);
+    return scan_impl<LoadPlain<uint32_t>, uint32_t>(LoadPlain<uint32_t>{data}, data, n, nullptr,
+                                                    scratch, s);
 }
 
 size_t radix_scratch_bytes(size_t n) {
@@ -293,7 +321,7 @@ size_t radix_scratch_bytes(size_t n) {
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
                             uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
-                            hipStream_t s) {
+                            hipStream_t s, const uint32_t *tag_counts) {
     *result_in_1 = false;
     if (n == 0) return hipSuccess;
     const uint32_t nb = (uint32_t)((n + kTile - 1) / kTile);
@@ -314,7 +342,8 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kT), 0, s, kin,
                            (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin, kout,
                            vout, n, n_dev, shift, bias, hist, nb,
-                           (!last || keys_needed) ? 1 : 0);
+                           (!last || keys_needed) ? 1 : 0,
+                           (p == 0 && vals_identity) ? tag_counts : nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         src ^= 1;
