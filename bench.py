@@ -31,8 +31,35 @@ FLOPS_EMISSION = 11   # weight (scale, exp) + per channel E*w, *T, +=
 FLOPS_ABSORBING = 29  # weight + per channel E*w, A*w, exp, 1-e, /x, *T*phi (2), +=, T*=
 
 
+SPLAT_KERNELS = {0: "k_splat_rows", 1: "k_splat_rows", 2: "k_splat_lists", 3: "k_splat_box"}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel, cfg, args):
+    """HBM bytes per launch of the dominant kernel from the committed
+    counter record (two rocprofv3 --pmc runs, FETCH_SIZE then WRITE_SIZE,
+    each scaled by the same counter's reading for a copy of known size), or
+    None when no record covers this kernel and workload or the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_lognormal_1e9_4096.json")
+    if not os.path.exists(path) or cfg.get("workload") != "lognormal_field":
+        return None
+    if cfg.get("n_target") != 1_000_000_000 or args.tile != 16 or args.max_pairs:
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def make_workload(args, torch):
@@ -167,9 +194,11 @@ def main():
     if dominant == "splat":
         flops = FLOPS_EMISSION * (n_mem - n_abs) + FLOPS_ABSORBING * n_abs
         ach = flops / (stages["splat"] * 1e-3) / 1e12
+        kern = SPLAT_KERNELS.get(args.splat_variant, "k_splat_rows")
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=None,
-                    kernel="k_splat", member_pairs=n_mem, member_pairs_absorbing=n_abs)
+                    unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                    traffic=measured_traffic(kern, cfg, args), kernel=kern,
+                    member_pairs=n_mem, member_pairs_absorbing=n_abs)
     else:
         algo_bytes = {
             "project": n * (24 + 4 + 1) + st["n_visible"] * 32 + n * 8,
