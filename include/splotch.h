@@ -161,6 +161,14 @@ typedef struct splotch_params {
                             3 = one wave per tile, pixel state in LDS, the
                                 lanes laid over each record's footprint box.
                             Other values: SPLOTCH_E_INVALID_ARG. */
+    int32_t batch_streams; /* splotch_render_batch only: views in flight at
+                            once, 0 or 1 = one after another on params->stream,
+                            2..4 = round-robin over that many streams (the
+                            caller's plus library-owned ones, forked from and
+                            joined back to params->stream).  The workspace is
+                            split into that many equal parts, each sized as
+                            splotch_workspace_size gives for one view.
+                            Other values: SPLOTCH_E_INVALID_ARG. */
     const uint8_t *tile_mask; /* device, one byte per screen tile (row-major,
                             tiles of params->tile px), or NULL = all tiles.
                             Tiles whose byte is 0 are skipped: no pairs, no
@@ -241,8 +249,9 @@ splotch_status splotch_bin(const splotch_particles *particles, const splotch_cam
  * call and replayed by later calls whose arguments (all pointers, sizes and
  * settings) are identical; params->stream must then be a created stream
  * (not the null stream).  The workspace is sized with
- * splotch_workspace_size for the view with the most tiles; views are
- * rendered one after another through it.  There is no chunking: a view
+ * splotch_workspace_size for the view with the most tiles, times
+ * params->batch_streams when that is above 1; views are rendered one after
+ * another through each part of it.  There is no chunking: a view
  * whose pairs exceed the workspace's pair capacity is left incomplete and
  * flagged.  params->tile_mask must be NULL (SPLOTCH_E_UNSUPPORTED).
  * If params->stats is not NULL it must point to n_views structs;

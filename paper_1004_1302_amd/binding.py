@@ -75,7 +75,8 @@ class Params(C.Structure):
                 ("sigma_over_h", C.c_float), ("trunc_f", C.c_float),
                 ("accumulate", C.c_int32), ("compensated", C.c_int32), ("tile", C.c_int32),
                 ("profile", C.c_int32), ("seg_records", C.c_int32),
-                ("splat_variant", C.c_int32), ("tile_mask", C.c_void_p),
+                ("splat_variant", C.c_int32), ("batch_streams", C.c_int32),
+                ("tile_mask", C.c_void_p),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats))]
 
@@ -175,7 +176,7 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
                   tile=0, profile=False, seg_records=0, tile_mask=None,
-                  splat_variant=0) -> Params:
+                  splat_variant=0, batch_streams=0) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
@@ -192,6 +193,7 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.seg_records = int(seg_records)
     p.tile_mask = None if tile_mask is None else C.c_void_p(tile_mask.data_ptr())
     p.splat_variant = int(splat_variant)
+    p.batch_streams = int(batch_streams)
     return p
 
 
@@ -356,12 +358,15 @@ def _side_stream(device):
 
 def render_batch(parts: dict, cams, palette, species, images=None, *, graph=False,
                  sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False, tile=0,
-                 max_pairs=0, seg_records=0, workspace=None, stats=False, splat_variant=0):
+                 max_pairs=0, seg_records=0, workspace=None, stats=False, splat_variant=0,
+                 streams=1):
     """Render several camera views of one particle set (splotch_render_batch).
     images: list of [3, H_v, W_v] float32 device tensors (allocated if None).
     graph=True captures the batch into a HIP graph on first use and replays
     it while every argument stays the same (same tensors, same settings).
-    Returns images, or (images, per-view stats) with stats=True."""
+    streams: views in flight at once (1..4); the workspace holds that many
+    view layouts.  Returns images, or (images, per-view stats) with
+    stats=True."""
     import torch
     P = particles_struct(parts)
     dev = parts["x"].device
@@ -371,11 +376,13 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
     cs = (CameraS * nv)(*[c if isinstance(c, CameraS) else camera_struct(c) for c in cams])
     prm = params_struct(species, sigma_over_h=sigma_over_h, trunc_f=trunc_f,
                         accumulate=accumulate, compensated=compensated, tile=tile,
-                        seg_records=seg_records, splat_variant=splat_variant)
+                        seg_records=seg_records, splat_variant=splat_variant,
+                        batch_streams=streams)
     T = tile or 16
     big = max(range(nv), key=lambda v: (-(-cs[v].width // T)) * (-(-cs[v].height // T)))
     if workspace is None:
-        need = workspace_bytes(P.n, cs[big], prm, max_pairs or 0)
+        one = workspace_bytes(P.n, cs[big], prm, max_pairs or 0)
+        need = (one + 255) // 256 * 256 * max(1, int(streams))
         workspace = get_workspace(need, dev)
         nbytes = need
     else:

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <list>
+#include <map>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -20,6 +21,7 @@ namespace {
 constexpr uint32_t kMaxChunks = 4096;
 constexpr uint64_t kMaxPairCap = 0xFFFF0000ull;  // pair indices are 32-bit
 constexpr uint32_t kSegMin = 1024;               // least records per list segment
+constexpr int kMaxLanes = 4;                     // batch views in flight at once
 
 struct Layout {
     size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
@@ -159,6 +161,7 @@ splotch_status validate_params(const splotch_params *p) {
     if (p->accumulate != 0 && p->accumulate != 1) return SPLOTCH_E_INVALID_ARG;
     if (p->seg_records < 0) return SPLOTCH_E_INVALID_ARG;
     if (p->splat_variant < 0 || p->splat_variant > 3) return SPLOTCH_E_INVALID_ARG;
+    if (p->batch_streams < 0 || p->batch_streams > kMaxLanes) return SPLOTCH_E_INVALID_ARG;
     for (int s = 0; s < p->n_species; ++s) {
         const splotch_species &q = p->species[s];
         if (q.mode != SPLOTCH_ADDITIVE && q.mode != SPLOTCH_ORDERED) return SPLOTCH_E_INVALID_ARG;
@@ -541,18 +544,42 @@ void key_bytes(std::vector<uint64_t> *k, const void *p, size_t n) {
     }
 }
 
-// Queue the whole batch on c.s without any host read-back.
-splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
-                             const splotch_camera *cams, const splotch_colourmap *cmap,
-                             const splotch_params *p, splotch_image *images) {
+// Library-owned streams and events for the batch lanes, one set per
+// device, created on first use (default priority).
+struct LaneSet {
+    hipStream_t s[kMaxLanes - 1];
+    hipEvent_t fork, join[kMaxLanes - 1];
+};
+std::mutex g_lane_mu;  // held while a batch is queued
+std::map<int, LaneSet> g_lanes;
+
+splotch_status lane_set(LaneSet **out) {
+    int dev = 0;
+    TRY(hipGetDevice(&dev));
+    auto it = g_lanes.find(dev);
+    if (it == g_lanes.end()) {
+        LaneSet L;
+        for (int k = 0; k < kMaxLanes - 1; ++k) {
+            TRY(hipStreamCreateWithFlags(&L.s[k], hipStreamNonBlocking));
+            TRY(hipEventCreateWithFlags(&L.join[k], hipEventDisableTiming));
+        }
+        TRY(hipEventCreateWithFlags(&L.fork, hipEventDisableTiming));
+        it = g_lanes.emplace(dev, L).first;
+    }
+    *out = &it->second;
+    return SPLOTCH_OK;
+}
+
+// Queue view v on lane c (its workspace part and stream).  flags/totals
+// (per view) live in the first lane's workspace part.
+splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals,
+                            const splotch_particles *P, const splotch_camera *cam,
+                            const splotch_colourmap *cmap, const splotch_params *p,
+                            splotch_image *image) {
     const int64_t n = P->n;
-    uint32_t *flags = c.at<uint32_t>(c.L.flags);
-    uint64_t *totals = reinterpret_cast<uint64_t *>(flags + SPLOTCH_MAX_VIEWS);
-    TRY(launch_fill_u32(flags, 0u, (size_t)nv, c.s));
     const uint64_t cap = c.L.pair_cap;
     const uint32_t nt = (uint32_t)(c.L.tile * c.L.tile);
-    for (int32_t v = 0; v < nv; ++v) {
-        const splotch_camera *cam = &cams[v];
+    {
         Layout Lv = c.L;  // same buffers; per-view tile grid
         Lv.ntx = (cam->width + c.L.tile - 1) / c.L.tile;
         Lv.nty = (cam->height + c.L.tile - 1) / c.L.tile;
@@ -622,7 +649,7 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         sa.palette = cmap->rgb;
         sa.n_pal = cmap->n_entries;
         sa.sp = species_dev(p);
-        sa.image = images[v].rgb;
+        sa.image = image->rgb;
         sa.member_count = c.at<unsigned long long>(c.L.mcount);
         sa.tile_mask = p->tile_mask;
         sa.range_bits = c.at<uint32_t>(c.L.range);
@@ -638,6 +665,36 @@ splotch_status enqueue_batch(Ctx &c, const splotch_particles *P, int32_t nv,
         const uint32_t q = 64;
         const uint32_t grid = (uint32_t)((Lv.n_tiles + kSegTarget + q - 1) / q * q);
         TRY(launch_splat(sa, grid, c.s));
+    }
+    return SPLOTCH_OK;
+}
+
+// Queue the whole batch without any host read-back: views round-robin over
+// the lanes (lane 0 runs on the caller's stream), forked from and joined
+// back to the caller's stream with events.
+splotch_status enqueue_batch(std::vector<Ctx> &lanes, const LaneSet *ls,
+                             const splotch_particles *P, int32_t nv, const splotch_camera *cams,
+                             const splotch_colourmap *cmap, const splotch_params *p,
+                             splotch_image *images) {
+    Ctx &c0 = lanes[0];
+    const int K = (int)lanes.size();
+    uint32_t *flags = c0.at<uint32_t>(c0.L.flags);
+    uint64_t *totals = reinterpret_cast<uint64_t *>(flags + SPLOTCH_MAX_VIEWS);
+    TRY(launch_fill_u32(flags, 0u, (size_t)nv, c0.s));
+    if (K > 1) {
+        TRY(hipEventRecord(ls->fork, c0.s));
+        for (int k = 1; k < K; ++k) TRY(hipStreamWaitEvent(lanes[k].s, ls->fork, 0));
+    }
+    for (int32_t v = 0; v < nv; ++v) {
+        splotch_status st = enqueue_view(lanes[v % K], v, flags, totals, P, &cams[v], cmap, p,
+                                         &images[v]);
+        if (st != SPLOTCH_OK) return st;
+    }
+    if (K > 1) {
+        for (int k = 1; k < K; ++k) {
+            TRY(hipEventRecord(ls->join[k - 1], lanes[k].s));
+            TRY(hipStreamWaitEvent(c0.s, ls->join[k - 1], 0));
+        }
     }
     return SPLOTCH_OK;
 }
@@ -865,13 +922,28 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
         }
     }
     if (!cmap || cmap->n_entries < 2 || !cmap->rgb) return SPLOTCH_E_INVALID_ARG;
+    if (p->batch_streams < 0 || p->batch_streams > kMaxLanes) return SPLOTCH_E_INVALID_ARG;
+    const int K = std::max(1, std::min<int>(p->batch_streams, n_views));
     Ctx c;
     splotch_params q = *p;  // stats are read after the batch, not per stage
     q.stats = nullptr;
+    q.workspace_bytes = p->workspace_bytes / (size_t)K / 256 * 256;  // one lane's part
     if ((st = prepare(P, &cams[big], &q, &c)) != SPLOTCH_OK) return st;
     if (use_graph && c.s == nullptr) return SPLOTCH_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lane_lock(g_lane_mu);
+    LaneSet *ls = nullptr;
+    std::vector<Ctx> lanes(K);
+    if (K > 1 && (st = lane_set(&ls)) != SPLOTCH_OK) return st;
+    for (int k = 0; k < K; ++k) {
+        lanes[k].L = c.L;
+        lanes[k].ws = c.ws + (size_t)k * q.workspace_bytes;
+        lanes[k].s = k == 0 ? c.s : ls->s[k - 1];
+        lanes[k].seg_min = c.seg_min;
+        lanes[k].tile_mask = c.tile_mask;
+    }
     if (!use_graph) {
-        if ((st = enqueue_batch(c, P, n_views, cams, cmap, p, images)) != SPLOTCH_OK) return st;
+        if ((st = enqueue_batch(lanes, ls, P, n_views, cams, cmap, p, images)) != SPLOTCH_OK)
+            return st;
     } else {
         std::vector<uint64_t> key;
         key_bytes(&key, P, sizeof *P);
@@ -889,7 +961,7 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
         if (it == g_graphs.end()) {
             hipGraph_t graph;
             TRY(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
-            st = enqueue_batch(c, P, n_views, cams, cmap, p, images);
+            st = enqueue_batch(lanes, ls, P, n_views, cams, cmap, p, images);
             hipError_t ec = hipStreamEndCapture(c.s, &graph);
             if (st != SPLOTCH_OK) {
                 if (ec == hipSuccess) (void)hipGraphDestroy(graph);

@@ -56,6 +56,36 @@ def test_batch_matches_single_views(scene, orc):
     assert np.all(rel <= 1e-4), rel
 
 
+@pytest.mark.parametrize("streams", [2, 3, 4])
+def test_batch_on_several_streams_matches_single_views(scene, streams):
+    """Views round-robin over several streams (each with its own workspace
+    part) give the same bits as one render call per view, eager and as a
+    replayed graph."""
+    import torch
+    parts, pal = B.scene_to_device(scene)
+    cams = orbit_cameras(7, 5, [(96, 96), (160, 120), (200, 90), (64, 128)])
+    refs = [single(parts, c, pal, scene.species_params) for c in cams]
+    imgs, st = B.render_batch(parts, cams, pal, scene.species_params, compensated=True,
+                              stats=True, streams=streams)
+    torch.cuda.synchronize()
+    for v in range(len(cams)):
+        assert np.array_equal(imgs[v].cpu().numpy(), refs[v]), f"view {v}"
+        assert st[v]["n_chunks"] == 1 and st[v]["n_pairs"] > 0
+    B.graph_cache_clear()
+    images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device="cuda")
+              for c in cams]
+    for rep in range(3):
+        for im in images:
+            im.fill_(-1.0)
+        torch.cuda.synchronize()
+        out = B.render_batch(parts, cams, pal, scene.species_params, images, graph=True,
+                             compensated=True, streams=streams)
+        torch.cuda.synchronize()
+        for v in range(len(cams)):
+            assert np.array_equal(out[v].cpu().numpy(), refs[v]), f"replay {rep} view {v}"
+    assert B.graph_cache_clear() == 1
+
+
 def test_graph_replays_track_eager(scene):
     """The captured graph is replayed several times with eager work and
     synchronisations in between; particle values change in place between
