@@ -94,12 +94,13 @@ __device__ __forceinline__ void composite(bool emit_only, float w, float e0, flo
         add_term<ORDERED, KAHAN>(C2, K2, T2, e2);
     } else {
         const float x0 = a0 * w, x1 = a1 * w, x2 = a2 * w;
+        // the series almost always; the rare large optical depth redoes its
+        // channels (one branch, skipped when no lane needs it)
         float ex0, ex1, ex2, ph0, ph1, ph2;
-        if (fmaxf(x0, fmaxf(x1, x2)) < kSeriesMax) {
-            ex_phi_small(x0, ex0, ph0);
-            ex_phi_small(x1, ex1, ph1);
-            ex_phi_small(x2, ex2, ph2);
-        } else {
+        ex_phi_small(x0, ex0, ph0);
+        ex_phi_small(x1, ex1, ph1);
+        ex_phi_small(x2, ex2, ph2);
+        if (fmaxf(x0, fmaxf(x1, x2)) >= kSeriesMax) {
             ex_phi(x0, ex0, ph0);
             ex_phi(x1, ex1, ph1);
             ex_phi(x2, ex2, ph2);
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
     if (tid < kMaxSpecies) species_range(a.sp, a.range_bits, tid, &s_vmin[tid], &s_vmax[tid]);
     __syncthreads();
 
-    uint64_t n_member = 0, n_absorb = 0;  // wave-uniform counts
+    uint32_t n_member = 0, n_absorb = 0;  // wave-uniform counts (< 2^32 per item)
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
     float T0 = 1.f, T1 = 1.f, T2 = 1.f;
@@ -437,14 +438,16 @@ __global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
                 const float dy = __builtin_fmaf(0.5f, ay, -f.y);
                 d2 = dx * dx + dy * dy;
             }
-            const bool in = ax >= 1.0f && ax <= g.z && ay >= 1.0f && ay <= g.w && d2 <= f.z;
+            // no short-circuit: one mask, no branch around the comparisons
+            const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
             const uint64_t mm = __ballot(in);
             if (mm == 0ull) continue;
             const float4 e = s_r[2][r];
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
-            n_member += (uint64_t)__popcll(mm);
-            if (ORDERED && !emit_only) n_absorb += (uint64_t)__popcll(mm);
+            const uint32_t nm = (uint32_t)__popcll(mm);
+            n_member += nm;
+            if (ORDERED && !emit_only) n_absorb += nm;
             if (!in) continue;
             const float w = __builtin_amdgcn_exp2f(-d2 * f.w);  // exp(-q^2)
             if (!ORDERED || emit_only) {
