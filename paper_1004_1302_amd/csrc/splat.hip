@@ -157,10 +157,9 @@ struct Expanded {
     float e[3], ab[3];
 };
 
-__device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t idx,
+__device__ __forceinline__ Expanded expand_loaded(const SplatArgs &a, uint4 ra, uint4 rb,
                                                   const float *vmin, const float *vmax) {
 #pragma clang fp contract(off)
-    const uint4 ra = a.rec[idx].a, rb = a.rec[idx].b;
     const int sp = (int)(ra.x >> 28);
     const float t = normalise_value(__uint_as_float(rb.z), vmin[sp], vmax[sp], a.sp.log_scale[sp]);
     const float rho0 = __uint_as_float(rb.w);
@@ -190,6 +189,11 @@ __device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t i
     x.ab[1] = ab * cg;
     x.ab[2] = ab * cb;
     return x;
+}
+
+__device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t idx,
+                                                  const float *vmin, const float *vmax) {
+    return expand_loaded(a, a.rec[idx].a, a.rec[idx].b, vmin, vmax);
 }
 
 // Records staged per batch: B indices of at most 8 bits per lane list.
@@ -344,28 +348,31 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 }
 
 // Row walk (one lane per pixel, state in registers).  Each wave owns an
-// 8x8 block of the tile.  A batch of up to 256 records is staged in LDS,
-// 64 bytes each, read back as four broadcast 16-byte rows:
+// 8x8 block of the tile and streams the item's list on its own, 64 records
+// at a time, with no barrier between waves (waves whose blocks see fewer
+// records do not wait for the others).  A chunk is staged in the wave's
+// own LDS rows, 64 bytes per record, read back as four broadcast 16-byte
+// rows:
 //   {u - i0, v - j0, r^2, log2(e)/sigma^2}, {2 i0, 2 j0, 2 (i1 - i0) + 1,
 //   2 (j1 - j0) + 1} as floats, {E c rho0, flags}, {A c rho0, 0}.
-// Every wave first lists, with ballots, the staged records whose box meets
-// its block, then walks only those, in order.  Membership: with
-// a = (2 i + 1) - 2 i0 = 2 (i - i0) + 1 (exact), a in [1, 2 (i1 - i0) + 1]
-// is the box test and fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0)
-// once, which is the binary32 offset of the index recipe bit for bit.
+// A ballot lists, in order, the chunk's records whose box meets the block;
+// the wave walks only those.  Membership: with a = (2 i + 1) - 2 i0 =
+// 2 (i - i0) + 1 (exact), a in [1, 2 (i1 - i0) + 1] is the box test and
+// fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0) once, which is
+// the binary32 offset of the index recipe bit for bit.
 template <int T, bool ORDERED, bool KAHAN>
-__global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
+__global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     constexpr int NT = T * T;
-    constexpr int NW = NT / 64;             // waves, one 8x8 block each
-    constexpr int QW = T / 8;               // blocks per tile row
-    constexpr int B = NT < 256 ? NT : 256;  // records per staged batch
-    __shared__ float4 s_r[4][B];
-    __shared__ uint32_t s_box[2][B];
-    __shared__ uint8_t s_wl[NW][B];
+    constexpr int NW = NT / 64;  // 8x8 blocks per tile, one workgroup of one wave each
+    constexpr int QW = T / 8;    // blocks per tile row
+    __shared__ float4 s_r[1][4][64];
+    __shared__ uint8_t s_wl[1][64];
     __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
-    __shared__ unsigned long long s_cnt[2][NW];
 
-    const uint32_t b = blockIdx.x, k = b >> 3;
+    // Workgroups are dealt to the 8 XCDs round-robin.  In each XCD's own
+    // sequence k, the NW blocks of an item come one after another (they
+    // read the same records, through that XCD's L2), items in runs of kRun.
+    const uint32_t b = blockIdx.x, k = (b >> 3) / NW, sub = (b >> 3) % NW;
     const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
     if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
@@ -374,8 +381,8 @@ __global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     const int tx0 = (int)(tile % (uint32_t)a.ntx) * T, ty0 = (int)(tile / (uint32_t)a.ntx) * T;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int bx = tx0 + (wave % QW) * 8, by = ty0 + (wave / QW) * 8;
+    const int lane = threadIdx.x, wave = 0;
+    const int bx = tx0 + (int)(sub % QW) * 8, by = ty0 + (int)(sub / QW) * 8;
     const int i = bx + (lane & 7), j = by + (lane >> 3);
     const float tfx = (float)(2 * i + 1), tfy = (float)(2 * j + 1);
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -383,53 +390,63 @@ __global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
     const uint32_t tend = a.tile_end[tile];
     const uint32_t start = a.tile_start[tile] + seg * seg_len;
     const uint32_t end = (tend - start) > seg_len ? start + seg_len : tend;
-    if (tid < kMaxSpecies) species_range(a.sp, a.range_bits, tid, &s_vmin[tid], &s_vmax[tid]);
+    if (lane < kMaxSpecies) species_range(a.sp, a.range_bits, lane, &s_vmin[lane], &s_vmax[lane]);
     __syncthreads();
 
     uint32_t n_member = 0, n_absorb = 0;  // wave-uniform counts (< 2^32 per item)
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
     float T0 = 1.f, T1 = 1.f, T2 = 1.f;
+    float4(*rows)[64] = s_r[wave];
 
-    for (uint32_t base = start; base < end; base += B) {
-        for (int r = tid; r < B; r += NT) {
-            if (base + r < end) {
-                const Expanded x = expand_record(a, a.pair_val[base + r], s_vmin, s_vmax);
-                const int i0 = (int)(x.b0 & kBboxMask), i1 = (int)((x.b0 >> kBboxBits) & kBboxMask);
-                const int j0 = (int)(x.b1 & kBboxMask), j1 = (int)((x.b1 >> kBboxBits) & kBboxMask);
-                s_r[0][r] = make_float4(x.ur, x.vr, x.r2, x.qs);
-                s_r[1][r] = make_float4((float)(2 * i0), (float)(2 * j0), (float)(2 * (i1 - i0) + 1),
+    // Software pipeline: while a chunk composites, the records of the next
+    // chunk and the pair indices of the one after are in flight.  Loads use
+    // positions clamped to the segment's last pair (always valid), so they
+    // land straight in these registers.
+    const uint32_t last = end > start ? end - 1 : start;
+    uint32_t idx_next = 0;
+    uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
+    if (end > start) {
+        const uint32_t p0 = start + lane, p1 = start + 64 + lane;
+        const uint32_t idx0 = a.pair_val[p0 < last ? p0 : last];
+        idx_next = a.pair_val[p1 < last ? p1 : last];
+        ra = a.rec[idx0].a;
+        rb = a.rec[idx0].b;
+    }
+    for (uint32_t base = start; base < end; base += 64) {
+        // stage this wave's chunk: lane l takes record base + l
+        bool hit = false;
+        if (base + lane < end) {
+            const Expanded x = expand_loaded(a, ra, rb, s_vmin, s_vmax);
+            const int i0 = (int)(x.b0 & kBboxMask), i1 = (int)((x.b0 >> kBboxBits) & kBboxMask);
+            const int j0 = (int)(x.b1 & kBboxMask), j1 = (int)((x.b1 >> kBboxBits) & kBboxMask);
+            rows[0][lane] = make_float4(x.ur, x.vr, x.r2, x.qs);
+            rows[1][lane] = make_float4((float)(2 * i0), (float)(2 * j0), (float)(2 * (i1 - i0) + 1),
                                         (float)(2 * (j1 - j0) + 1));
-                s_r[2][r] = make_float4(x.e[0], x.e[1], x.e[2], __uint_as_float(x.b1 & ~kRowMask));
-                s_r[3][r] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
-                s_box[0][r] = x.b0;
-                s_box[1][r] = x.b1;
-            }
+            rows[2][lane] = make_float4(x.e[0], x.e[1], x.e[2], __uint_as_float(x.b1 & ~kRowMask));
+            rows[3][lane] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
+            hit = i1 >= bx && i0 <= bx + 7 && j1 >= by && j0 <= by + 7;
         }
-        __syncthreads();
-        const int nb = (int)((end - base) < (uint32_t)B ? (end - base) : (uint32_t)B);
-        // this wave's list: staged records whose box meets its block, in order
-        int cnt = 0;
-        for (int c = 0; c < nb; c += 64) {
-            const int r = c + lane;
-            bool hit = false;
-            if (r < nb) {
-                const uint32_t b0 = s_box[0][r], b1 = s_box[1][r];
-                const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
-                const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
-                hit = i1 >= bx && i0 <= bx + 7 && j1 >= by && j0 <= by + 7;
-            }
-            const uint64_t m = __ballot(hit);
-            if (hit) s_wl[wave][cnt + __popcll(m & below)] = (uint8_t)r;
-            cnt += __popcll(m);
+        // issued after the expansion's own loads, so that waiting for those
+        // does not wait for these
+        {
+            const uint32_t p2 = base + 128 + lane;
+            ra = a.rec[idx_next].a;
+            rb = a.rec[idx_next].b;
+            idx_next = a.pair_val[p2 < last ? p2 : last];
         }
-        // the wave reads back its own list (a wave's LDS requests complete in order)
+        // the chunk's records whose box meets this wave's block, in order
+        const uint64_t m = __ballot(hit);
+        if (hit) s_wl[wave][__popcll(m & below)] = (uint8_t)lane;
+        const int cnt = __popcll(m);
+        // the wave reads back its own rows and list (a wave's LDS requests
+        // complete in order)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int q = 0; q < cnt; ++q) {
             const int r = __builtin_amdgcn_readfirstlane((int)s_wl[wave][q]);
-            const float4 g = s_r[1][r];
-            const float4 f = s_r[0][r];
+            const float4 g = rows[1][r];
+            const float4 f = rows[0][r];
             const float ax = tfx - g.x, ay = tfy - g.y;
             float d2;
             {
@@ -442,7 +459,7 @@ __global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
             const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
             const uint64_t mm = __ballot(in);
             if (mm == 0ull) continue;
-            const float4 e = s_r[2][r];
+            const float4 e = rows[2][r];
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
             const uint32_t nm = (uint32_t)__popcll(mm);
@@ -457,27 +474,19 @@ __global__ __launch_bounds__(T *T) void k_splat_rows(SplatArgs a) {
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, e.x, e.y, e.z, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             } else {
-                const float4 x = s_r[3][r];
+                const float4 x = rows[3][r];
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             }
         }
-        __syncthreads();
+        // before the next chunk overwrites this wave's rows and list
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (lane == 0) {
-        s_cnt[0][wave] = n_member;
-        s_cnt[1][wave] = n_absorb;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long t = 0, ta = 0;
-        for (int w = 0; w < NW; ++w) {
-            t += s_cnt[0][w];
-            ta += s_cnt[1][w];
-        }
         // statistics only; compositing itself uses no atomics
-        if (t) atomicAdd(&a.member_count[2 * tile], t);
-        if (ta) atomicAdd(&a.member_count[2 * tile + 1], ta);
+        if (n_member) atomicAdd(&a.member_count[2 * tile], (unsigned long long)n_member);
+        if (n_absorb) atomicAdd(&a.member_count[2 * tile + 1], (unsigned long long)n_absorb);
     }
     if (nseg == 1) {
         write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
@@ -726,8 +735,9 @@ template <int T, bool ORDERED, bool KAHAN>
 hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     switch (a.variant) {
         case kSplatRows:
-            hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
-                               a);
+            // one single-wave workgroup per 8x8 block of every item
+            hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN>), dim3(grid * (T * T / 64)),
+                               dim3(64), 0, s, a);
             break;
         case kSplatLists:
             hipLaunchKernelGGL((k_splat_lists<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
