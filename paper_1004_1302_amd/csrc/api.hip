@@ -381,7 +381,7 @@ splotch_status run_order_and_scan(const Ctx &c, int64_t n, bool trim_keys,
 // tile ranges.  Returns the sorted pair values via *vals.
 splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, uint32_t idx_mask,
                              uint64_t first, uint64_t last, uint64_t off_first, uint64_t npairs,
-                             const uint32_t **vals) {
+                             const uint32_t **vals, const uint32_t **keys_out = nullptr) {
     uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
     uint32_t *pv0 = c.at<uint32_t>(c.L.pv0), *pv1 = c.at<uint32_t>(c.L.pv1);
     EmitArgs e;
@@ -396,6 +396,7 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, uint32_t idx_m
     e.overflow = nullptr;
     e.tile_mask = c.tile_mask;
     e.tile = c.L.tile;
+    e.qshift = block_mask_shift(c.L.tile, c.L.n_tiles);
     e.ntx = c.L.ntx;
     e.pair_key = pk0;
     e.pair_val = pv0;
@@ -408,8 +409,10 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, uint32_t idx_m
                          c.at<void>(c.L.radix), &in1, c.s));
     const uint32_t *keys = in1 ? pk1 : pk0;
     *vals = in1 ? pv1 : pv0;
+    const uint32_t key_mask = e.qshift ? (1u << e.qshift) - 1u : 0xFFFFFFFFu;
     TRY(launch_tile_ranges(keys, (size_t)npairs, nullptr, c.at<uint32_t>(c.L.tstart),
-                           c.at<uint32_t>(c.L.tend), c.L.n_tiles, c.s));
+                           c.at<uint32_t>(c.L.tend), c.L.n_tiles, key_mask, c.s));
+    if (keys_out) *keys_out = keys;
     TRY(const_cast<Prof &>(c.prof).mark(4));
     return SPLOTCH_OK;
 }
@@ -612,6 +615,7 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         e.tile_mask = p->tile_mask;
         e.tile = c.L.tile;
         e.ntx = Lv.ntx;
+        e.qshift = block_mask_shift(c.L.tile, Lv.n_tiles);
         uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
         uint32_t *pv0 = c.at<uint32_t>(c.L.pv0), *pv1 = c.at<uint32_t>(c.L.pv1);
         e.pair_key = pk0;
@@ -627,7 +631,8 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         const uint32_t *keys = in1 ? pk1 : pk0;
         const uint32_t *vals = in1 ? pv1 : pv0;
         uint32_t *ts = c.at<uint32_t>(c.L.tstart), *te = c.at<uint32_t>(c.L.tend);
-        TRY(launch_tile_ranges(keys, (size_t)cap, total, ts, te, Lv.n_tiles, c.s));
+        TRY(launch_tile_ranges(keys, (size_t)cap, total, ts, te, Lv.n_tiles,
+                               e.qshift ? (1u << e.qshift) - 1u : 0xFFFFFFFFu, c.s));
         TRY(launch_segments(ts, te, Lv.n_tiles, cap, total, nt, c.seg_min,
                             c.at<uint32_t>(c.L.seg_len), c.at<uint32_t>(c.L.nseg),
                             c.at<uint32_t>(c.L.nmulti), c.at<uint64_t>(c.L.seg_off),
@@ -637,6 +642,8 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         memset(&sa, 0, sizeof sa);
         sa.rec = c.at<Rec>(c.L.rec);
         sa.pair_val = vals;
+        sa.pair_key = keys;
+        sa.qshift = e.qshift;
         sa.tile_start = ts;
         sa.tile_end = te;
         sa.seg_off = c.at<uint64_t>(c.L.seg_off);
@@ -820,6 +827,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.max_slots = c.L.max_slots;
     sa.max_items = c.L.max_items;
     sa.seg_len = c.at<uint32_t>(c.L.seg_len);
+    sa.qshift = block_mask_shift(c.L.tile, c.L.n_tiles);
     TRY(launch_fill_u32(c.at<uint32_t>(c.L.mcount), 0u, (size_t)c.L.n_tiles * 4, c.s));
 
     const uint64_t total = plan.back();
@@ -828,6 +836,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
         TRY(launch_fill_u32(c.at<uint32_t>(c.L.tstart), 0u, c.L.n_tiles, c.s));
         TRY(launch_fill_u32(c.at<uint32_t>(c.L.tend), 0u, c.L.n_tiles, c.s));
         sa.pair_val = c.at<uint32_t>(c.L.pv0);
+        sa.pair_key = c.at<uint32_t>(c.L.pk0);
         sa.accumulate = p->accumulate;
         if ((st = run_splat_pass(c, sa, 0)) != SPLOTCH_OK) return st;
         return read_stats(c, p, 0, 0);
@@ -837,11 +846,12 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
         const int k = c.L.ordered ? nch - 1 - q : q;
         const uint64_t first = plan[2 * k], last = plan[2 * k + 2];
         const uint64_t o0 = plan[2 * k + 1], o1 = plan[2 * k + 3];
-        const uint32_t *vals;
-        if ((st = run_bin_chunk(c, order, idx_mask, first, last, o0, o1 - o0, &vals)) !=
+        const uint32_t *vals, *keys;
+        if ((st = run_bin_chunk(c, order, idx_mask, first, last, o0, o1 - o0, &vals, &keys)) !=
             SPLOTCH_OK)
             return st;
         sa.pair_val = vals;
+        sa.pair_key = keys;
         sa.accumulate = q == 0 ? p->accumulate : 1;
         if ((st = run_splat_pass(c, sa, o1 - o0)) != SPLOTCH_OK) return st;
     }

@@ -34,11 +34,24 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     // write the pairs that fit, so every slot below the capacity holds a
     // valid pair, and flag the pass.
     if (o + c > a.cap && a.overflow) *a.overflow = 1u;
+    const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
+    const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
+    const int QW = T / 8;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
             if (a.tile_mask && !a.tile_mask[ty * a.ntx + tx]) continue;
             if (o >= a.cap) return;
-            a.pair_key[o] = (uint32_t)(ty * a.ntx + tx);
+            uint32_t key = (uint32_t)(ty * a.ntx + tx);
+            if (a.qshift) {
+                // the tile's 8x8 blocks the box meets: a rectangle of them
+                const int qx0 = (max(i0, tx * T) - tx * T) >> 3, qx1 = (min(i1, tx * T + T - 1) - tx * T) >> 3;
+                const int qy0 = (max(j0, ty * T) - ty * T) >> 3, qy1 = (min(j1, ty * T + T - 1) - ty * T) >> 3;
+                const uint32_t row = ((2u << qx1) - 1u) & ~((1u << qx0) - 1u);
+                uint32_t m = 0;
+                for (int qy = qy0; qy <= qy1; ++qy) m |= row << (qy * QW);
+                key |= m << a.qshift;
+            }
+            a.pair_key[o] = key;
             a.pair_val[o] = i;
             ++o;
         }
@@ -47,7 +60,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
 // Boundaries of each tile's run in the sorted pair keys.  Each thread
 // takes four consecutive keys (one 16-byte load) plus its right neighbour.
 __global__ void k_tile_ranges(const uint32_t *keys, size_t n_cap, const uint64_t *n_dev,
-                              uint32_t *start, uint32_t *end, uint32_t n_tiles) {
+                              uint32_t *start, uint32_t *end, uint32_t n_tiles,
+                              uint32_t key_mask) {
     size_t n = n_cap;
     if (n_dev && *n_dev < n) n = (size_t)*n_dev;
     const size_t nq = (n + 3) / 4;
@@ -57,15 +71,15 @@ __global__ void k_tile_ranges(const uint32_t *keys, size_t n_cap, const uint64_t
         uint32_t k[5];
         if (p0 + 4 <= n) {
             const uint4 v = *reinterpret_cast<const uint4 *>(keys + p0);
-            k[0] = v.x;
-            k[1] = v.y;
-            k[2] = v.z;
-            k[3] = v.w;
+            k[0] = v.x & key_mask;
+            k[1] = v.y & key_mask;
+            k[2] = v.z & key_mask;
+            k[3] = v.w & key_mask;
         } else {
-            for (int j = 0; j < 4; ++j) k[j] = p0 + j < n ? keys[p0 + j] : 0xFFFFFFFFu;
+            for (int j = 0; j < 4; ++j) k[j] = p0 + j < n ? (keys[p0 + j] & key_mask) : 0xFFFFFFFFu;
         }
-        const uint32_t prev = p0 > 0 ? keys[p0 - 1] : 0xFFFFFFFFu;
-        k[4] = p0 + 4 < n ? keys[p0 + 4] : 0xFFFFFFFFu;
+        const uint32_t prev = p0 > 0 ? (keys[p0 - 1] & key_mask) : 0xFFFFFFFFu;
+        k[4] = p0 + 4 < n ? (keys[p0 + 4] & key_mask) : 0xFFFFFFFFu;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const size_t p = p0 + j;
@@ -142,13 +156,13 @@ hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
 
 hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs,
                               const uint64_t *n_pairs_dev, uint32_t *start, uint32_t *end,
-                              uint32_t n_tiles, hipStream_t s) {
+                              uint32_t n_tiles, uint32_t key_mask, hipStream_t s) {
     hipError_t e = launch_fill_u32(start, 0u, n_tiles, s);
     if (e != hipSuccess) return e;
     e = launch_fill_u32(end, 0u, n_tiles, s);
     if (e != hipSuccess || n_pairs == 0) return e;
     hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for((n_pairs + 3) / 4, 1u << 20)), dim3(kThreads), 0, s,
-                       sorted_keys, n_pairs, n_pairs_dev, start, end, n_tiles);
+                       sorted_keys, n_pairs, n_pairs_dev, start, end, n_tiles, key_mask);
     return hipGetLastError();
 }
 

@@ -120,13 +120,27 @@ struct EmitArgs {
     uint32_t *overflow;      // may be null when cap is known to suffice
     int tile, ntx;
     const uint8_t *tile_mask;  // per tile, 0 = skip; null = all tiles
+    int qshift;                // > 0: key bit qshift + b set when the box meets 8x8 block b
     uint32_t *pair_key, *pair_val;
 };
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
+// Bit of a pair key where the mask of the tile's 8x8 blocks that the
+// particle's box meets begins (bit qshift + b for block b, row-major), or 0
+// when tiles have one block or the tile sort's 8-bit digits reach those bits.
+inline int block_mask_shift(int tile, uint32_t n_tiles) {
+    const int nb = (tile / 8) * (tile / 8);
+    if (nb <= 1 || nb > 24) return 0;
+    int bits = 0;
+    while ((1ull << bits) < (uint64_t)n_tiles) ++bits;
+    const int sorted = (bits + 7) / 8 * 8;
+    const int qs = 32 - nb;
+    return sorted <= qs ? qs : 0;
+}
 // n_pairs_dev (nullable): live pair count on the device, capped at n_pairs.
+// key_mask: the bits of a pair key that hold the tile index.
 hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs,
                               const uint64_t *n_pairs_dev, uint32_t *start, uint32_t *end,
-                              uint32_t n_tiles, hipStream_t s);
+                              uint32_t n_tiles, uint32_t key_mask, hipStream_t s);
 hipError_t launch_chunk_plan(const uint64_t *off, uint64_t n, uint64_t capacity,
                              uint64_t *bounds, uint32_t max_chunks, hipStream_t s);
 
@@ -137,6 +151,8 @@ hipError_t launch_chunk_plan(const uint64_t *off, uint64_t n, uint64_t capacity,
 struct SplatArgs {
     const Rec *rec;
     const uint32_t *pair_val;
+    const uint32_t *pair_key;   // sorted keys (block masks from bit qshift)
+    int qshift;                 // see EmitArgs; 0 = no block masks
     const uint32_t *tile_start, *tile_end;
     const uint64_t *seg_off;    // [n_tiles + 1] first item of each tile
     const uint64_t *part_off;   // [n_tiles + 1] first partial slot of each multi-segment tile

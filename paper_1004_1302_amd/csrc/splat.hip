@@ -348,16 +348,20 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 }
 
 // Row walk (one lane per pixel, state in registers).  Each wave owns an
-// 8x8 block of the tile and streams the item's list on its own, 64 records
-// at a time, with no barrier between waves (waves whose blocks see fewer
-// records do not wait for the others).  A chunk is staged in the wave's
-// own LDS rows, 64 bytes per record, read back as four broadcast 16-byte
-// rows:
+// 8x8 block of the tile and streams the item's list on its own, with no
+// barrier between waves (waves whose blocks see fewer records do not wait
+// for the others).  Pair keys carry, above the tile index, the mask of the
+// tile's blocks that the particle's box meets: the wave scans keys 256 at
+// a time and queues, in list order, the particle indices of the pairs
+// whose mask holds its block, so it gathers and expands only those.  Up to
+// 64 queued records at a time are staged in the wave's own LDS rows,
+// 64 bytes per record, read back as four broadcast 16-byte rows:
 //   {u - i0, v - j0, r^2, log2(e)/sigma^2}, {2 i0, 2 j0, 2 (i1 - i0) + 1,
 //   2 (j1 - j0) + 1} as floats, {E c rho0, flags}, {A c rho0, 0}.
-// A ballot lists, in order, the chunk's records whose box meets the block;
-// the wave walks only those.  Membership: with a = (2 i + 1) - 2 i0 =
-// 2 (i - i0) + 1 (exact), a in [1, 2 (i1 - i0) + 1] is the box test and
+// Without block masks (one block per tile, or tile indices that need the
+// bits) every pair is queued; the per-pixel box test below keeps the
+// result the same.  Membership: with a = (2 i + 1) - 2 i0 = 2 (i - i0) + 1
+// (exact), a in [1, 2 (i1 - i0) + 1] is the box test and
 // fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0) once, which is
 // the binary32 offset of the index recipe bit for bit.
 template <int T, bool ORDERED, bool KAHAN>
@@ -365,13 +369,15 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;  // 8x8 blocks per tile, one workgroup of one wave each
     constexpr int QW = T / 8;    // blocks per tile row
-    __shared__ float4 s_r[1][4][64];
-    __shared__ uint8_t s_wl[1][64];
+    constexpr uint32_t kQ = 512;  // queue ring: < 64 left over + 256 scanned
+    __shared__ float4 s_r[4][64];
+    __shared__ uint32_t s_q[kQ];
     __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
 
     // Workgroups are dealt to the 8 XCDs round-robin.  In each XCD's own
     // sequence k, the NW blocks of an item come one after another (they
-    // read the same records, through that XCD's L2), items in runs of kRun.
+    // read the same keys and records, through that XCD's L2), items in runs
+    // of kRun.
     const uint32_t b = blockIdx.x, k = (b >> 3) / NW, sub = (b >> 3) % NW;
     const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     const int tx0 = (int)(tile % (uint32_t)a.ntx) * T, ty0 = (int)(tile / (uint32_t)a.ntx) * T;
-    const int lane = threadIdx.x, wave = 0;
+    const int lane = threadIdx.x;
     const int bx = tx0 + (int)(sub % QW) * 8, by = ty0 + (int)(sub / QW) * 8;
     const int i = bx + (lane & 7), j = by + (lane >> 3);
     const float tfx = (float)(2 * i + 1), tfy = (float)(2 * j + 1);
@@ -397,56 +403,75 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
     float T0 = 1.f, T1 = 1.f, T2 = 1.f;
-    float4(*rows)[64] = s_r[wave];
 
-    // Software pipeline: while a chunk composites, the records of the next
-    // chunk and the pair indices of the one after are in flight.  Loads use
-    // positions clamped to the segment's last pair (always valid), so they
-    // land straight in these registers.
+    // Keys and values of the next 256 positions are loaded one scan ahead,
+    // at positions clamped to the segment's last pair (always valid).
+    const bool masked = a.qshift != 0;
+    const uint32_t bit = masked ? (uint32_t)a.qshift + sub : 0u;
     const uint32_t last = end > start ? end - 1 : start;
-    uint32_t idx_next = 0;
+    uint32_t kq[4] = {0u, 0u, 0u, 0u}, vq[4] = {0u, 0u, 0u, 0u};
+    uint32_t pos = start;
+    auto load_scan = [&](uint32_t p) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t q = p + 64 * c + lane;
+            const uint32_t qc = q < last ? q : last;
+            if (masked) kq[c] = a.pair_key[qc];
+            vq[c] = a.pair_val[qc];
+        }
+    };
+    uint32_t head = 0, qn = 0;  // queue ring: entries [head, head + qn)
+    auto fill = [&]() {
+        while (qn < 64 && pos < end) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bool hit = pos + 64 * c + lane < end && (!masked || ((kq[c] >> bit) & 1u));
+                const uint64_t m = __ballot(hit);
+                if (hit) s_q[(head + qn + __popcll(m & below)) & (kQ - 1)] = vq[c];
+                qn += (uint32_t)__popcll(m);
+            }
+            pos += 256;
+            if (pos < end) load_scan(pos);
+        }
+    };
+    if (end > start) load_scan(start);
+    fill();
+    // the records of the next batch are in flight while a batch composites
     uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
-    if (end > start) {
-        const uint32_t p0 = start + lane, p1 = start + 64 + lane;
-        const uint32_t idx0 = a.pair_val[p0 < last ? p0 : last];
-        idx_next = a.pair_val[p1 < last ? p1 : last];
-        ra = a.rec[idx0].a;
-        rb = a.rec[idx0].b;
-    }
-    for (uint32_t base = start; base < end; base += 64) {
-        // stage this wave's chunk: lane l takes record base + l
-        bool hit = false;
-        if (base + lane < end) {
+    auto gather = [&](uint32_t n) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((uint32_t)lane < n) {
+            const uint32_t idx = s_q[(head + lane) & (kQ - 1)];
+            ra = a.rec[idx].a;
+            rb = a.rec[idx].b;
+        }
+        head += n;
+        qn -= n;
+    };
+    uint32_t ncur = qn < 64 ? qn : 64;
+    gather(ncur);
+    while (ncur > 0) {
+        if ((uint32_t)lane < ncur) {
             const Expanded x = expand_loaded(a, ra, rb, s_vmin, s_vmax);
             const int i0 = (int)(x.b0 & kBboxMask), i1 = (int)((x.b0 >> kBboxBits) & kBboxMask);
             const int j0 = (int)(x.b1 & kBboxMask), j1 = (int)((x.b1 >> kBboxBits) & kBboxMask);
-            rows[0][lane] = make_float4(x.ur, x.vr, x.r2, x.qs);
-            rows[1][lane] = make_float4((float)(2 * i0), (float)(2 * j0), (float)(2 * (i1 - i0) + 1),
-                                        (float)(2 * (j1 - j0) + 1));
-            rows[2][lane] = make_float4(x.e[0], x.e[1], x.e[2], __uint_as_float(x.b1 & ~kRowMask));
-            rows[3][lane] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
-            hit = i1 >= bx && i0 <= bx + 7 && j1 >= by && j0 <= by + 7;
+            s_r[0][lane] = make_float4(x.ur, x.vr, x.r2, x.qs);
+            s_r[1][lane] = make_float4((float)(2 * i0), (float)(2 * j0), (float)(2 * (i1 - i0) + 1),
+                                       (float)(2 * (j1 - j0) + 1));
+            s_r[2][lane] = make_float4(x.e[0], x.e[1], x.e[2], __uint_as_float(x.b1 & ~kRowMask));
+            s_r[3][lane] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
         }
-        // issued after the expansion's own loads, so that waiting for those
-        // does not wait for these
-        {
-            const uint32_t p2 = base + 128 + lane;
-            ra = a.rec[idx_next].a;
-            rb = a.rec[idx_next].b;
-            idx_next = a.pair_val[p2 < last ? p2 : last];
-        }
-        // the chunk's records whose box meets this wave's block, in order
-        const uint64_t m = __ballot(hit);
-        if (hit) s_wl[wave][__popcll(m & below)] = (uint8_t)lane;
-        const int cnt = __popcll(m);
-        // the wave reads back its own rows and list (a wave's LDS requests
-        // complete in order)
+        fill();
+        const uint32_t nnext = qn < 64 ? qn : 64;
+        gather(nnext);
+        // the wave reads back its own rows (a wave's LDS requests complete
+        // in order)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int q = 0; q < cnt; ++q) {
-            const int r = __builtin_amdgcn_readfirstlane((int)s_wl[wave][q]);
-            const float4 g = rows[1][r];
-            const float4 f = rows[0][r];
+        for (uint32_t r = 0; r < ncur; ++r) {
+            const float4 g = s_r[1][r];
+            const float4 f = s_r[0][r];
             const float ax = tfx - g.x, ay = tfy - g.y;
             float d2;
             {
@@ -459,7 +484,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
             const uint64_t mm = __ballot(in);
             if (mm == 0ull) continue;
-            const float4 e = rows[2][r];
+            const float4 e = s_r[2][r];
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
             const uint32_t nm = (uint32_t)__popcll(mm);
@@ -474,14 +499,15 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, e.x, e.y, e.z, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             } else {
-                const float4 x = rows[3][r];
+                const float4 x = s_r[3][r];
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             }
         }
-        // before the next chunk overwrites this wave's rows and list
+        // before the next batch overwrites the rows
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ncur = nnext;
     }
     if (lane == 0) {
         // statistics only; compositing itself uses no atomics
