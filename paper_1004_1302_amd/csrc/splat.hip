@@ -399,7 +399,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     if (lane < kMaxSpecies) species_range(a.sp, a.range_bits, lane, &s_vmin[lane], &s_vmax[lane]);
     __syncthreads();
 
-    uint32_t n_member = 0, n_absorb = 0;  // wave-uniform counts (< 2^32 per item)
+    uint32_t n_member = 0, n_absorb = 0;  // this lane's contributions
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
     float T0 = 1.f, T1 = 1.f, T2 = 1.f;
@@ -482,24 +482,20 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             }
             // no short-circuit: one mask, no branch around the comparisons
             const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
-            const uint64_t mm = __ballot(in);
-            if (mm == 0ull) continue;
+            if (__ballot(in) == 0ull) continue;
             const float4 e = s_r[2][r];
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
-            const uint32_t nm = (uint32_t)__popcll(mm);
-            n_member += nm;
-            if (ORDERED && !emit_only) n_absorb += nm;
             if (!in) continue;
+            ++n_member;
             const float w = __builtin_amdgcn_exp2f(-d2 * f.w);  // exp(-q^2)
             if (!ORDERED || emit_only) {
                 composite<ORDERED, KAHAN>(true, w, e.x, e.y, e.z, 0.f, 0.f, 0.f, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
-            } else if (flags & kEmitEqAbsorb) {
-                composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, e.x, e.y, e.z, C0, C1, C2, K0,
-                                          K1, K2, T0, T1, T2);
             } else {
-                const float4 x = s_r[3][r];
+                ++n_absorb;
+                // E = A: the emission row doubles as the absorption row
+                const float4 x = s_r[(flags & kEmitEqAbsorb) ? 2 : 3][r];
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             }
@@ -508,6 +504,10 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         ncur = nnext;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        n_member += __shfl_xor(n_member, o, 64);
+        n_absorb += __shfl_xor(n_absorb, o, 64);
     }
     if (lane == 0) {
         // statistics only; compositing itself uses no atomics
