@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--splat-variant", type=int, default=0)
     ap.add_argument("--max-pairs", type=float, default=0)
-    ap.add_argument("--cpu-sample", type=float, default=2_000_000)
+    ap.add_argument("--cpu-sample", type=float, default=5_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -469,7 +469,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
         // in order)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t r = 0; r < ncur; ++r) {
+        auto visit = [&](uint32_t r) {
             const float4 g = s_r[1][r];
             const float4 f = s_r[0][r];
             const float ax = tfx - g.x, ay = tfy - g.y;
@@ -482,11 +482,11 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             }
             // no short-circuit: one mask, no branch around the comparisons
             const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
-            if (__ballot(in) == 0ull) continue;
+            if (__ballot(in) == 0ull) return;
             const float4 e = s_r[2][r];
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
-            if (!in) continue;
+            if (!in) return;
             ++n_member;
             const float w = __builtin_amdgcn_exp2f(-d2 * f.w);  // exp(-q^2)
             if (!ORDERED || emit_only) {
@@ -499,7 +499,15 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             }
+        };
+        // two visits per trip: the register allocator alternates the
+        // running sums between them instead of copying them back each trip
+        uint32_t r = 0;
+        for (; r + 1 < ncur; r += 2) {
+            visit(r);
+            visit(r + 1);
         }
+        if (r < ncur) visit(r);
         // before the next batch overwrites the rows
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -116,6 +116,22 @@ def edge_scene():
     return synth.Scene(x, y, z, h, v, cam, sp, species=spc, rho0=r0, name="edges")
 
 
+def wide_scene(w, h, n=200_000, seed=12):
+    """Mixed species over an orthographic w x h view, footprints of a few
+    pixels (sigma about 3 px) whatever the image size."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    y = rng.uniform(0.5 - 0.6 * h / w, 0.5 + 0.6 * h / w, n).astype(np.float32)
+    z = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    hh = rng.lognormal(np.log(3.0 / w), 0.5, n).astype(np.float32)
+    v = rng.lognormal(0, 1, n).astype(np.float32)
+    sp = [synth.Species(log_scale=1, brightness=0.6, absorption=0.6, mode=synth.ORDERED),
+          synth.Species(brightness=0.4, mode=synth.ADDITIVE)]
+    spc = rng.integers(0, 2, n).astype(np.uint8)
+    return synth.Scene(x, y, z, hh, v, synth.ortho_unit_square(w, h), sp, species=spc,
+                       name=f"wide_{w}x{h}")
+
+
 # ----------------------------------------------------------------- indices
 @pytest.mark.parametrize("name", ["c1", "c2_small", "edges"])
 @pytest.mark.parametrize("tile", [8, 16, 32])
@@ -234,6 +250,31 @@ def test_box_mapped_lanes_chunked(torch_cuda, orc):
     img, st = gpu_render(scene, max_pairs=5000, stats=True, splat_variant=3)
     assert st["n_chunks"] > 3
     check_image(img, orc.render(scene))
+
+
+def test_block_masks_on_and_off_bitwise_equal(torch_cuda):
+    """Pair keys carry the mask of the tile's 8x8 blocks a footprint meets
+    when the tile index leaves room above the sort's digits: 16 px tiles
+    here, and 32 px tiles of a small image.  On a 16384 x 4160 image the
+    66,560 tiles of 32 px need 17 bits, the sort orders 24, and the masks
+    are off (every pair queued for every block); 8 px tiles never carry
+    masks.  With one list segment per tile each pixel composites the same
+    particles in the same order through the same arithmetic, so all of
+    these images are bit-identical."""
+    kw = dict(compensated=True, seg_records=1 << 24, splat_variant=1, max_pairs=1 << 24,
+              stats=True)
+
+    def one(scene, tile):
+        img, st = gpu_render(scene, tile=tile, **kw)
+        assert st["n_chunks"] == 1, (tile, st["n_pairs"])
+        return img
+
+    for w, h in ((16384, 4160), (480, 270)):
+        scene = wide_scene(w, h)
+        ref = one(scene, 16)
+        assert np.any(ref > 0)
+        for tile in (32, 8):
+            assert np.array_equal(one(scene, tile), ref), (w, tile)
 
 
 @pytest.mark.parametrize("spread", [0.0, 1e-6, 0.25])
