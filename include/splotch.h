@@ -310,6 +310,24 @@ splotch_status splotch_nn_epilogue(const float *partials, int32_t splits, int64_
                                    const float *residual, uint16_t *out_bf16, float *out_f32,
                                    void *stream);
 
+/* Forward-convolution weights: wf[co][tap*cin + ci] = w[tap*cin + ci][co]
+ * (w is the GEMM operand [9*cin][cout]; wf is [cout][9*cin], bf16). */
+splotch_status splotch_nn_conv3x3_weights(const uint16_t *w, uint16_t *wf, int32_t cin,
+                                          int32_t cout, void *stream);
+
+/* Fused 3x3 convolution, stride 1, zero padding, NHWC bf16 x [n][h][w][cin]:
+ * out[p][co] = act(sum over taps and ci of x[p + offset(tap)][ci] *
+ * wf[co][tap*cin + ci] + bias[co]) + residual[p][co], with the epilogue of
+ * splotch_nn_epilogue and the same meaning of relu, bias, residual and the
+ * two outputs.  The same result as im2col + GEMM + epilogue up to the order
+ * of the FP32 accumulation, without the [n*h*w][9*cin] patch buffer.
+ * cin and cout are multiples of 32; wf comes from splotch_nn_conv3x3_weights.
+ * Device pointers, caller-owned; asynchronous on stream. */
+splotch_status splotch_nn_conv3x3(const uint16_t *x, const uint16_t *wf, const float *bias,
+                                  int32_t relu, const float *residual, uint16_t *out_bf16,
+                                  float *out_f32, int32_t n, int32_t h, int32_t w, int32_t cin,
+                                  int32_t cout, void *stream);
+
 /* ReLU adjoint: dz = dy where y > 0 (or everywhere when relu = 0), as bf16
  * and optionally float32. */
 splotch_status splotch_nn_relu_bwd(const float *dy, const uint16_t *y, int32_t relu,

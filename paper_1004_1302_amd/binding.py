@@ -91,6 +91,7 @@ EXPORTS = ("splotch_status_string", "splotch_camera_look_at", "splotch_workspace
            "splotch_render", "splotch_project", "splotch_bin", "splotch_render_batch",
            "splotch_graph_cache_clear", "splotch_nn_gemm", "splotch_nn_gemm_splits",
            "splotch_nn_im2col3x3", "splotch_nn_flip_weights", "splotch_nn_epilogue",
+           "splotch_nn_conv3x3_weights", "splotch_nn_conv3x3",
            "splotch_nn_relu_bwd", "splotch_nn_colsum", "splotch_nn_pool2", "splotch_nn_pool2_bwd",
            "splotch_nn_up2_concat", "splotch_nn_up2_concat_bwd", "splotch_nn_mse",
            "splotch_nn_adam", "splotch_nn_tonemap", "splotch_nn_untonemap",

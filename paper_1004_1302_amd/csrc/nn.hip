@@ -117,6 +117,116 @@ __global__ __launch_bounds__(256) void k_gemm(const bf16_t *A, const bf16_t *B, 
         }
 }
 
+// ------------------------------------------------------- fused 3x3 convolution
+// Forward weights [cout][9 cin] from the GEMM operand [9 cin][cout]: row n
+// holds output channel n's taps (tap-major, then input channel), so a
+// lane's 8 consecutive reduction terms are one 16-byte read.
+__global__ void k_conv_wf(const bf16_t *w, bf16_t *wf, int cin, int cout) {
+    const size_t k9 = (size_t)9 * cin, total = k9 * cout;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const size_t n = e / k9, k = e % k9;
+        wf[e] = w[k * cout + n];
+    }
+}
+
+// out = epilogue(conv3x3(x, W) + bias) for NHWC BF16 x, without an im2col
+// buffer: the implicit GEMM (pixels x cout, reduction over 9 taps x cin)
+// runs on the matrix cores from LDS.  A workgroup owns an 8 x 16 pixel
+// tile and CO output channels; per 32-channel slice of the input it stages
+// the tile with its one-pixel halo (zeros outside the image) and the
+// slice's weights for all 9 taps, then each wave accumulates 2 rows of 16
+// pixels x CO channels, one MFMA per (row, 16 channels) per tap.
+constexpr int kCTH = 8, kCTW = 16;           // output tile rows, columns
+constexpr int kCHW = kCTW + 2;               // halo tile width
+constexpr int kCHP = (kCTH + 2) * kCHW;      // halo tile pixels
+constexpr int kCK = 32;                      // input channels per stage
+constexpr int kCRow = kCK + PAD;             // LDS row (bf16); 80 B spreads the banks
+
+template <int CO>
+__global__ __launch_bounds__(256) void k_conv3x3(const bf16_t *x, const bf16_t *wf,
+                                                 const float *bias, int relu,
+                                                 const float *residual, bf16_t *out_bf,
+                                                 float *out_f, int h, int w, int cin, int cout) {
+    constexpr int NT = CO / 16;
+    __shared__ __attribute__((aligned(16))) bf16_t sX[kCHP][kCRow];
+    __shared__ __attribute__((aligned(16))) bf16_t sW[9 * CO][kCRow];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (w + kCTW - 1) / kCTW, tiles_y = (h + kCTH - 1) / kCTH;
+    const int tile = (int)(blockIdx.x % (unsigned)(tiles_x * tiles_y));
+    const int img = (int)(blockIdx.x / (unsigned)(tiles_x * tiles_y));
+    const int y0 = (tile / tiles_x) * kCTH, x0 = (tile % tiles_x) * kCTW;
+    const int n0 = (int)blockIdx.y * CO;
+    const size_t k9 = (size_t)9 * cin;
+    const size_t plane = (size_t)img * h;
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kq = (lane >> 4) * 8;
+    for (int c0 = 0; c0 < cin; c0 += kCK) {
+        __syncthreads();  // the previous slice's fragments are read
+        for (int e = tid; e < kCHP * 4; e += 256) {
+            const int p = e >> 2, q = (e & 3) * 8;
+            const int yy = y0 - 1 + p / kCHW, xx = x0 - 1 + p % kCHW;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                v = *reinterpret_cast<const uint4 *>(x + ((plane + yy) * w + xx) * cin + c0 + q);
+            *reinterpret_cast<uint4 *>(&sX[p][q]) = v;
+        }
+        for (int e = tid; e < 9 * CO * 4; e += 256) {
+            const int r = e >> 2, q = (e & 3) * 8;
+            const int tap = r / CO, nl = r % CO;
+            *reinterpret_cast<uint4 *>(&sW[r][q]) = *reinterpret_cast<const uint4 *>(
+                wf + (size_t)(n0 + nl) * k9 + (size_t)tap * cin + c0 + q);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8 af[2], bfr[NT];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                af[a] = *reinterpret_cast<const bf16x8 *>(
+                    &sX[(2 * wave + a + dy) * kCHW + (lane & 15) + dx][kq]);
+#pragma unroll
+            for (int b = 0; b < NT; ++b)
+                bfr[b] = *reinterpret_cast<const bf16x8 *>(&sW[tap * CO + b * 16 + (lane & 15)][kq]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < NT; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b],
+                                                                        0, 0, 0);
+        }
+    }
+    // output (pixel, channel) of acc[a][b][q]: row 2 wave + a, column
+    // 4 (lane / 16) + q of the tile; channel n0 + 16 b + lane % 16
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int yy = y0 + 2 * wave + a;
+        if (yy >= h) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int xx = x0 + (lane >> 4) * 4 + q;
+            if (xx >= w) continue;
+            const size_t pix = (plane + yy) * w + xx;
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const int n = n0 + b * 16 + (lane & 15);
+                const size_t e = pix * cout + n;
+                float v = acc[a][b][q];
+                if (bias) v += bias[n];
+                if (relu) v = v > 0.f ? v : 0.f;
+                if (residual) v += residual[e];
+                if (out_bf) out_bf[e] = f2bf(v);
+                if (out_f) out_f[e] = v;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ im2col
 // out[p][tap*C + c] = in[p shifted by tap][c] (zero outside the image),
 // taps in (ky, kx) row-major order, p = (img, y, x).
@@ -411,6 +521,28 @@ hipError_t epilogue(const float *Cp, int splits, size_t mn, int n, const float *
                     const float *residual, bf16_t *out_bf, float *out_f, hipStream_t s) {
     hipLaunchKernelGGL(k_epilogue, dim3(grid_for(mn)), dim3(256), 0, s, Cp, splits, mn, n, bias,
                        relu, residual, out_bf, out_f);
+    return hipGetLastError();
+}
+
+hipError_t conv3x3_weights(const bf16_t *w, bf16_t *wf, int cin, int cout, hipStream_t s) {
+    const size_t total = (size_t)9 * cin * cout;
+    hipLaunchKernelGGL(k_conv_wf, dim3(grid_for(total)), dim3(256), 0, s, w, wf, cin, cout);
+    return hipGetLastError();
+}
+
+hipError_t conv3x3(const bf16_t *x, const bf16_t *wf, const float *bias, int relu,
+                   const float *residual, bf16_t *out_bf, float *out_f, int n, int h, int w,
+                   int cin, int cout, hipStream_t s) {
+    const unsigned tiles = (unsigned)((h + kCTH - 1) / kCTH) * (unsigned)((w + kCTW - 1) / kCTW);
+    if (cout % 64 == 0) {
+        hipLaunchKernelGGL(k_conv3x3<64>, dim3(tiles * (unsigned)n, (unsigned)(cout / 64)),
+                           dim3(256), 0, s, x, wf, bias, relu, residual, out_bf, out_f, h, w, cin,
+                           cout);
+    } else {
+        hipLaunchKernelGGL(k_conv3x3<32>, dim3(tiles * (unsigned)n, (unsigned)(cout / 32)),
+                           dim3(256), 0, s, x, wf, bias, relu, residual, out_bf, out_f, h, w, cin,
+                           cout);
+    }
     return hipGetLastError();
 }
 

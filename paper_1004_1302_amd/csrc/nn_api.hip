@@ -44,6 +44,25 @@ splotch_status splotch_nn_epilogue(const float *partials, int32_t splits, int64_
                        out_f32, st(stream)));
 }
 
+splotch_status splotch_nn_conv3x3_weights(const uint16_t *w, uint16_t *wf, int32_t cin,
+                                         int32_t cout, void *stream) {
+    if (!w || !wf || cin <= 0 || cout <= 0) return SPLOTCH_E_INVALID_ARG;
+    return ok(conv3x3_weights(w, wf, cin, cout, st(stream)));
+}
+
+splotch_status splotch_nn_conv3x3(const uint16_t *x, const uint16_t *wf, const float *bias,
+                                  int32_t relu, const float *residual, uint16_t *out_bf16,
+                                  float *out_f32, int32_t n, int32_t h, int32_t w, int32_t cin,
+                                  int32_t cout, void *stream) {
+    if (!x || !wf || (!out_bf16 && !out_f32) || n <= 0 || h <= 0 || w <= 0)
+        return SPLOTCH_E_INVALID_ARG;
+    if (cin <= 0 || cin % 32 || cout <= 0 || cout % 32) return SPLOTCH_E_INVALID_ARG;
+    const uint64_t tiles = (uint64_t)((h + 7) / 8) * (uint64_t)((w + 15) / 16) * (uint64_t)n;
+    if (tiles >= (1ull << 31)) return SPLOTCH_E_INVALID_ARG;
+    return ok(conv3x3(x, wf, bias, relu ? 1 : 0, residual, out_bf16, out_f32, n, h, w, cin, cout,
+                      st(stream)));
+}
+
 splotch_status splotch_nn_relu_bwd(const float *dy, const uint16_t *y, int32_t relu,
                                    uint16_t *dz_bf16, float *dz_f32, int64_t n, void *stream) {
     if (!dy || !dz_bf16 || n <= 0 || (relu && !y)) return SPLOTCH_E_INVALID_ARG;

@@ -15,6 +15,12 @@ hipError_t gemm(const bf16_t *A, const bf16_t *B, float *C, int M, int N, int K,
 int gemm_splits(int K, int splits);
 hipError_t im2col3x3(const bf16_t *in, bf16_t *out, int n, int h, int w, int c, hipStream_t s);
 hipError_t flip_weights(const bf16_t *w, bf16_t *wt, int cout, int cin, hipStream_t s);
+// Fused 3x3 convolution (zero padding) with the epilogue below: cin and cout
+// multiples of 32; wf from conv3x3_weights ([cout][9 cin]).
+hipError_t conv3x3_weights(const bf16_t *w, bf16_t *wf, int cin, int cout, hipStream_t s);
+hipError_t conv3x3(const bf16_t *x, const bf16_t *wf, const float *bias, int relu,
+                   const float *residual, bf16_t *out_bf, float *out_f, int n, int h, int w,
+                   int cin, int cout, hipStream_t s);
 hipError_t epilogue(const float *Cp, int splits, size_t mn, int n, const float *bias, int relu,
                     const float *residual, bf16_t *out_bf, float *out_f, hipStream_t s);
 hipError_t relu_bwd(const float *dy, const bf16_t *y, int relu, bf16_t *dz_bf, float *dz_f,

@@ -43,6 +43,8 @@ def _lib():
             "splotch_nn_im2col3x3": [P, P, I32, I32, I32, I32, P],
             "splotch_nn_flip_weights": [P, P, I32, I32, P],
             "splotch_nn_epilogue": [P, I32, I64, I32, P, I32, P, P, P, P],
+            "splotch_nn_conv3x3_weights": [P, P, I32, I32, P],
+            "splotch_nn_conv3x3": [P, P, P, I32, P, P, P, I32, I32, I32, I32, I32, P],
             "splotch_nn_relu_bwd": [P, P, I32, P, P, I64, P],
             "splotch_nn_colsum": [P, I64, I32, P, P, P],
             "splotch_nn_pool2": [P, P, I32, I32, I32, I32, P],
@@ -103,6 +105,15 @@ class Ops:
     def epilogue(self, Cp, splits, rows, cols, bias, relu, residual, out_bf, out_f):
         _ok(self.L.splotch_nn_epilogue(_p(Cp), splits, rows, cols, _p(bias), int(relu),
                                        _p(residual), _p(out_bf), _p(out_f), _s()), "nn_epilogue")
+
+    def conv_weights(self, w, wf, cin, cout):
+        _ok(self.L.splotch_nn_conv3x3_weights(_p(w), _p(wf), cin, cout, _s()),
+            "nn_conv3x3_weights")
+
+    def conv3x3(self, x, wf, bias, relu, residual, out_bf, out_f, n, h, w, cin, cout):
+        _ok(self.L.splotch_nn_conv3x3(_p(x), _p(wf), _p(bias), int(relu), _p(residual),
+                                      _p(out_bf), _p(out_f), n, h, w, cin, cout, _s()),
+            "nn_conv3x3")
 
     def relu_bwd(self, dy, y, relu, dz_bf, dz_f, n):
         _ok(self.L.splotch_nn_relu_bwd(_p(dy), _p(y), int(relu), _p(dz_bf), _p(dz_f), n, _s()),
@@ -166,7 +177,8 @@ class Scratch:
 class Conv3x3:
     """3x3 convolution, stride 1, zero padding.  Master weights in FP32 laid
     out as the GEMM operand [9*cin][cout] (tap-major, then input channel),
-    with a BF16 copy; FP32 bias; Adam moments."""
+    with a BF16 copy and its [cout][9*cin] transpose for the fused forward
+    kernel; FP32 bias; Adam moments."""
 
     def __init__(self, cin, cout, relu, rng, device, gain=1.0):
         import torch
@@ -177,6 +189,7 @@ class Conv3x3:
         self.b = torch.zeros(cout, dtype=torch.float32, device=device)
         self.w_bf = torch.empty((9 * cin, cout), dtype=torch.int16, device=device)
         self.wt_bf = torch.empty((9 * cout, cin), dtype=torch.int16, device=device)
+        self.wf_bf = torch.empty((cout, 9 * cin), dtype=torch.int16, device=device)
         self.gw = torch.empty_like(self.w)
         self.gb = torch.empty_like(self.b)
         self.mw = torch.zeros_like(self.w)
@@ -184,19 +197,19 @@ class Conv3x3:
         self.mb = torch.zeros_like(self.b)
         self.vb = torch.zeros_like(self.b)
         self.ops = Ops()
+        self.refresh_bf16()
+
+    def refresh_bf16(self):
+        """BF16 copies of the master weights (after init, load or a step)."""
         self.ops.f2bf(self.w, self.w_bf, self.w.numel())
+        self.ops.conv_weights(self.w_bf, self.wf_bf, self.cin, self.cout)
 
     def n_params(self):
         return self.w.numel() + self.b.numel()
 
     def forward(self, x_bf, n, h, w, out_bf, sc, tag, out_f=None, residual=None):
-        P = n * h * w
-        col = sc.get("col", P * 9 * self.cin, self.w_bf.dtype)
-        self.ops.im2col(x_bf, col, n, h, w, self.cin)
-        cbuf = sc.get("gemm", P * self.cout, self.w.dtype)
-        self.ops.gemm(col, self.w_bf, cbuf, P, self.cout, 9 * self.cin, 9 * self.cin, self.cout,
-                      0, 1)
-        self.ops.epilogue(cbuf, 1, P, self.cout, self.b, self.relu, residual, out_bf, out_f)
+        self.ops.conv3x3(x_bf, self.wf_bf, self.b, self.relu, residual, out_bf, out_f, n, h, w,
+                         self.cin, self.cout)
 
     def backward(self, x_bf, y_bf, dy, n, h, w, sc, need_dx):
         """dy: FP32 gradient of this layer's output.  Fills gw, gb and returns
@@ -229,6 +242,7 @@ class Conv3x3:
                       eps, step)
         self.ops.adam(self.b, None, self.gb, self.mb, self.vb, self.b.numel(), lr, b1, b2, eps,
                       step)
+        self.ops.conv_weights(self.w_bf, self.wf_bf, self.cin, self.cout)
 
 
 class UNet:
@@ -364,7 +378,7 @@ class UNet:
         for k, c in enumerate(self.layers()):
             c.w.copy_(torch.from_numpy(d[f"w{k}"]))
             c.b.copy_(torch.from_numpy(d[f"b{k}"]))
-            c.ops.f2bf(c.w, c.w_bf, c.w.numel())
+            c.refresh_bf16()
 
 
 # ------------------------------------------------------------------ data

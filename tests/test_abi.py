@@ -210,3 +210,24 @@ def test_batch_validates_before_launch():
     assert lib.splotch_render_batch(C.byref(P), 2, cams, C.byref(cm), C.byref(prm), ims, 0) == 2
     assert lib.splotch_render_batch(C.byref(P), 2, cams, C.byref(cm), C.byref(prm), ims, 3) == 1
     assert B.graph_cache_clear() == 0
+
+
+def test_fused_conv_argument_checks():
+    """Host-side checks of the fused convolution's arguments, before any
+    launch: channel counts must be multiples of 32, sizes positive, and at
+    least one output given."""
+    import ctypes as C
+    from paper_1004_1302_amd import learned as LN
+    L = LN._lib()
+    p = C.c_void_p(16)
+    bad = [
+        (p, p, None, 1, None, p, None, 1, 8, 16, 48, 32),   # cin % 32
+        (p, p, None, 1, None, p, None, 1, 8, 16, 32, 40),   # cout % 32
+        (p, p, None, 1, None, None, None, 1, 8, 16, 32, 32),  # no output
+        (None, p, None, 1, None, p, None, 1, 8, 16, 32, 32),  # no input
+        (p, p, None, 1, None, p, None, 0, 8, 16, 32, 32),   # n = 0
+        (p, p, None, 1, None, p, None, 1, 8, -1, 32, 32),   # w < 0
+    ]
+    for args in bad:
+        assert L.splotch_nn_conv3x3(*args, None) == 1, args  # SPLOTCH_E_INVALID_ARG
+    assert L.splotch_nn_conv3x3_weights(None, p, 32, 32, None) == 1

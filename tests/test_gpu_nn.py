@@ -55,6 +55,49 @@ def test_gemm_bf16_mfma(torch, M, N, K, trans, splits):
     assert np.allclose(got, ref, rtol=1e-5, atol=1e-4 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n,h,w,ci,co,relu,res", [
+    (1, 13, 21, 32, 32, True, False), (2, 16, 24, 96, 128, True, False),
+    (1, 9, 40, 64, 32, False, True), (1, 32, 32, 256, 128, True, False),
+    (3, 8, 16, 32, 64, True, True)])
+def test_fused_conv3x3(torch, n, h, w, ci, co, relu, res):
+    """The fused convolution (halo tile and weights in LDS, implicit GEMM on
+    the matrix cores) against the FP64 reference on the same BF16 operands,
+    and against im2col + GEMM + epilogue: ragged tiles, several images,
+    several 32-channel slices, both channel groupings, residual input."""
+    rng = np.random.default_rng(ci + co + h)
+    ops = LN.Ops()
+    P = n * h * w
+    xb, x64 = to_bf16_bits(torch, rng.standard_normal((P, ci)))
+    wb, w64 = to_bf16_bits(torch, rng.standard_normal((9 * ci, co)) * math.sqrt(2.0 / (9 * ci)))
+    b = rng.standard_normal(co).astype(np.float32) * 0.1
+    bt = torch.from_numpy(b).cuda()
+    r = rng.standard_normal((P, co)).astype(np.float32) if res else None
+    rt = torch.from_numpy(r).cuda() if res else None
+    wf = torch.empty((co, 9 * ci), dtype=torch.int16, device="cuda")
+    ops.conv_weights(wb, wf, ci, co)
+    out_f = torch.full((P, co), float("nan"), dtype=torch.float32, device="cuda")
+    out_b = torch.zeros((P, co), dtype=torch.int16, device="cuda")
+    ops.conv3x3(xb, wf, bt, relu, rt, out_b, out_f, n, h, w, ci, co)
+    col = torch.empty((P, 9 * ci), dtype=torch.int16, device="cuda")
+    ops.im2col(xb, col, n, h, w, ci)
+    cb = torch.empty((P, co), dtype=torch.float32, device="cuda")
+    ops.gemm(col, wb, cb, P, co, 9 * ci, 9 * ci, co, 0, 1)
+    ref_f = torch.empty((P, co), dtype=torch.float32, device="cuda")
+    ops.epilogue(cb, 1, P, co, bt, relu, rt, None, ref_f)
+    torch.cuda.synchronize()
+    z = R.conv3x3(x64.reshape(n, h, w, ci), w64.reshape(9, ci, co), b.astype(np.float64))
+    if relu:
+        z = np.maximum(z, 0)
+    if res:
+        z = z + r.reshape(n, h, w, co)
+    got = out_f.cpu().numpy().reshape(n, h, w, co)
+    scale = np.abs(z).max()
+    assert np.abs(got - z).max() <= 1e-5 * scale
+    assert np.abs(got - ref_f.cpu().numpy().reshape(n, h, w, co)).max() <= 1e-5 * scale
+    gb = bits_to_f64(out_b).reshape(n, h, w, co)
+    assert np.array_equal(gb, R.bf16(got.astype(np.float64)))
+
+
 def test_conv_layer_forward_backward(torch):
     rng = np.random.default_rng(5)
     n, h, w, ci, co = 2, 16, 24, 32, 64
