@@ -321,7 +321,8 @@ splotch_status splotch_nn_conv3x3_weights(const uint16_t *w, uint16_t *wf, int32
  * splotch_nn_epilogue and the same meaning of relu, bias, residual and the
  * two outputs.  The same result as im2col + GEMM + epilogue up to the order
  * of the FP32 accumulation, without the [n*h*w][9*cin] patch buffer.
- * cin and cout are multiples of 32; wf comes from splotch_nn_conv3x3_weights.
+ * cin and cout are multiples of 32, x and wf 16-byte aligned; wf comes from
+ * splotch_nn_conv3x3_weights.
  * Device pointers, caller-owned; asynchronous on stream. */
 splotch_status splotch_nn_conv3x3(const uint16_t *x, const uint16_t *wf, const float *bias,
                                   int32_t relu, const float *residual, uint16_t *out_bf16,
@@ -339,7 +340,8 @@ splotch_status splotch_nn_colsum(const float *in, int64_t rows, int32_t cols, fl
                                  float *scratch, void *stream);
 
 /* 2x2 average pool [n][h][w][c] -> [n][h/2][w/2][c] (bf16) and its adjoint
- * (float32; accumulate adds into din). */
+ * (float32; accumulate adds into din).  The forward pool takes c a multiple
+ * of 8 and 16-byte aligned in and out. */
 splotch_status splotch_nn_pool2(const uint16_t *in, uint16_t *out, int32_t n, int32_t h, int32_t w,
                                 int32_t c, void *stream);
 splotch_status splotch_nn_pool2_bwd(const float *dout, float *din, int32_t n, int32_t h,
@@ -347,7 +349,9 @@ splotch_status splotch_nn_pool2_bwd(const float *dout, float *din, int32_t n, in
 
 /* Nearest 2x upsample of a ([n][h/2][w/2][ca]) concatenated along channels
  * with s ([n][h][w][cs]) into out ([n][h][w][ca+cs]), and its adjoint:
- * da = 2x2 sums of the first ca channels, ds = the other cs channels. */
+ * da = 2x2 sums of the first ca channels, ds = the other cs channels.
+ * The forward takes ca and cs multiples of 8 and 16-byte aligned a, s and
+ * out. */
 splotch_status splotch_nn_up2_concat(const uint16_t *a, int32_t ca, const uint16_t *s, int32_t cs,
                                      uint16_t *out, int32_t n, int32_t h, int32_t w,
                                      void *stream);

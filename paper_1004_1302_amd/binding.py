@@ -247,6 +247,16 @@ def get_workspace(nbytes: int, device):
     return t
 
 
+def reserve_workspace(parts: dict, cam, species, max_pairs=0, **kw):
+    """Grow the cached workspace, on the current stream, to what a render of
+    these particles needs, so that a later render (on any stream) does not
+    replace it."""
+    P = particles_struct(parts)
+    cs = cam if isinstance(cam, CameraS) else camera_struct(cam)
+    return get_workspace(workspace_bytes(P.n, cs, params_struct(species, **kw), max_pairs),
+                         parts["x"].device)
+
+
 def release_workspace():
     _ws_cache.clear()
 

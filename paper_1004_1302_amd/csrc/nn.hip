@@ -319,18 +319,31 @@ __global__ void k_colsum_final(const float *part, int nblocks, int cols, float *
 }
 
 // 2x2 average pool (NHWC, BF16 in/out) and its adjoint (FP32 in/out).
+// Eight channels per thread (one 16-byte load per input pixel).
 __global__ void k_pool2(const bf16_t *in, bf16_t *out, int n, int h, int w, int c) {
-    const int ho = h / 2, wo = w / 2;
-    const size_t total = (size_t)n * ho * wo * c;
+    const int ho = h / 2, wo = w / 2, c8 = c / 8;
+    const size_t total = (size_t)n * ho * wo * c8;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int ch = (int)(e % c);
-        size_t p = e / c;
+        const int ch = (int)(e % c8) * 8;
+        size_t p = e / c8;
         const int x = (int)(p % wo), y = (int)((p / wo) % ho), img = (int)(p / ((size_t)wo * ho));
         const size_t b = (((size_t)img * h + 2 * y) * w + 2 * x) * c + ch;
-        const float s = bf2f(in[b]) + bf2f(in[b + c]) + bf2f(in[b + (size_t)w * c]) +
-                        bf2f(in[b + (size_t)w * c + c]);
-        out[e] = f2bf(0.25f * s);
+        const size_t row = (size_t)w * c;
+        union U {
+            uint4 v;
+            bf16_t s[8];
+        } q0, q1, q2, q3, o;
+        q0.v = *reinterpret_cast<const uint4 *>(in + b);
+        q1.v = *reinterpret_cast<const uint4 *>(in + b + c);
+        q2.v = *reinterpret_cast<const uint4 *>(in + b + row);
+        q3.v = *reinterpret_cast<const uint4 *>(in + b + row + c);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float sum = bf2f(q0.s[k]) + bf2f(q1.s[k]) + bf2f(q2.s[k]) + bf2f(q3.s[k]);
+            o.s[k] = f2bf(0.25f * sum);
+        }
+        *reinterpret_cast<uint4 *>(out + p * c + ch) = o.v;
     }
 }
 
@@ -349,17 +362,21 @@ __global__ void k_pool2_bwd(const float *dout, float *din, int n, int h, int w, 
 
 // Nearest 2x upsample of `a` (ca channels, h/2 x w/2) concatenated with
 // `s` (cs channels, h x w) along channels: out has ca + cs channels.
+// Eight channels per thread; ca and cs are multiples of 8, so a group of
+// eight never straddles the two sources.
 __global__ void k_up2_concat(const bf16_t *a, int ca, const bf16_t *s, int cs, bf16_t *out, int n,
                              int h, int w) {
-    const int co = ca + cs;
-    const size_t total = (size_t)n * h * w * co;
+    const int co = ca + cs, c8 = co / 8;
+    const size_t total = (size_t)n * h * w * c8;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int ch = (int)(e % co);
-        size_t p = e / co;
+        const int ch = (int)(e % c8) * 8;
+        size_t p = e / c8;
         const int x = (int)(p % w), y = (int)((p / w) % h), img = (int)(p / ((size_t)w * h));
-        out[e] = ch < ca ? a[(((size_t)img * (h / 2) + y / 2) * (w / 2) + x / 2) * ca + ch]
-                         : s[p * cs + (ch - ca)];
+        const bf16_t *src = ch < ca
+            ? a + (((size_t)img * (h / 2) + y / 2) * (w / 2) + x / 2) * ca + ch
+            : s + p * cs + (ch - ca);
+        *reinterpret_cast<uint4 *>(out + p * co + ch) = *reinterpret_cast<const uint4 *>(src);
     }
 }
 
@@ -566,7 +583,7 @@ hipError_t colsum(const float *in, size_t rows, int cols, float *out, float *par
 }
 
 hipError_t pool2(const bf16_t *in, bf16_t *out, int n, int h, int w, int c, hipStream_t s) {
-    hipLaunchKernelGGL(k_pool2, dim3(grid_for((size_t)n * h * w * c / 4)), dim3(256), 0, s, in,
+    hipLaunchKernelGGL(k_pool2, dim3(grid_for((size_t)n * h * w * c / 32)), dim3(256), 0, s, in,
                        out, n, h, w, c);
     return hipGetLastError();
 }
@@ -580,7 +597,7 @@ hipError_t pool2_bwd(const float *dout, float *din, int n, int h, int w, int c, 
 
 hipError_t up2_concat(const bf16_t *a, int ca, const bf16_t *sk, int cs, bf16_t *out, int n,
                       int h, int w, hipStream_t s) {
-    hipLaunchKernelGGL(k_up2_concat, dim3(grid_for((size_t)n * h * w * (ca + cs))), dim3(256), 0,
+    hipLaunchKernelGGL(k_up2_concat, dim3(grid_for((size_t)n * h * w * (ca + cs) / 8)), dim3(256), 0,
                        s, a, ca, sk, cs, out, n, h, w);
     return hipGetLastError();
 }

@@ -8,6 +8,8 @@ namespace {
 inline hipStream_t st(void *s) { return reinterpret_cast<hipStream_t>(s); }
 inline splotch_status ok(hipError_t e) { return e == hipSuccess ? SPLOTCH_OK : SPLOTCH_E_DEVICE; }
 inline bool m8(int v) { return v > 0 && v % 8 == 0; }
+// 16-byte aligned (the vectorised kernels move eight bf16 at a time)
+inline bool a16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 }  // namespace
 
 extern "C" {
@@ -57,6 +59,7 @@ splotch_status splotch_nn_conv3x3(const uint16_t *x, const uint16_t *wf, const f
     if (!x || !wf || (!out_bf16 && !out_f32) || n <= 0 || h <= 0 || w <= 0)
         return SPLOTCH_E_INVALID_ARG;
     if (cin <= 0 || cin % 32 || cout <= 0 || cout % 32) return SPLOTCH_E_INVALID_ARG;
+    if (!a16(x) || !a16(wf)) return SPLOTCH_E_INVALID_ARG;
     const uint64_t tiles = (uint64_t)((h + 7) / 8) * (uint64_t)((w + 15) / 16) * (uint64_t)n;
     if (tiles >= (1ull << 31)) return SPLOTCH_E_INVALID_ARG;
     return ok(conv3x3(x, wf, bias, relu ? 1 : 0, residual, out_bf16, out_f32, n, h, w, cin, cout,
@@ -78,8 +81,9 @@ splotch_status splotch_nn_colsum(const float *in, int64_t rows, int32_t cols, fl
 
 splotch_status splotch_nn_pool2(const uint16_t *in, uint16_t *out, int32_t n, int32_t h, int32_t w,
                                 int32_t c, void *stream) {
-    if (!in || !out || n <= 0 || h <= 0 || w <= 0 || h % 2 || w % 2 || c <= 0)
+    if (!in || !out || n <= 0 || h <= 0 || w <= 0 || h % 2 || w % 2 || !m8(c))
         return SPLOTCH_E_INVALID_ARG;
+    if (!a16(in) || !a16(out)) return SPLOTCH_E_INVALID_ARG;
     return ok(pool2(in, out, n, h, w, c, st(stream)));
 }
 
@@ -93,8 +97,9 @@ splotch_status splotch_nn_pool2_bwd(const float *dout, float *din, int32_t n, in
 splotch_status splotch_nn_up2_concat(const uint16_t *a, int32_t ca, const uint16_t *s, int32_t cs,
                                      uint16_t *out, int32_t n, int32_t h, int32_t w,
                                      void *stream) {
-    if (!a || !s || !out || ca <= 0 || cs <= 0 || n <= 0 || h % 2 || w % 2)
+    if (!a || !s || !out || !m8(ca) || !m8(cs) || n <= 0 || h <= 0 || w <= 0 || h % 2 || w % 2)
         return SPLOTCH_E_INVALID_ARG;
+    if (!a16(a) || !a16(s) || !a16(out)) return SPLOTCH_E_INVALID_ARG;
     return ok(up2_concat(a, ca, s, cs, out, n, h, w, st(stream)));
 }
 

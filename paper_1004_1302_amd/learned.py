@@ -486,22 +486,68 @@ def probe_mask(width, height, tile, frac, seed, device):
     return torch.from_numpy(m).to(device), m.reshape(nty, ntx)
 
 
+_probe_cache = {}
+
+
+def _probe_sel(width, height, tile, frac, seed, device):
+    """probe_mask plus the flat indices of the probed pixels (device), cached
+    per setting so that a frame uploads nothing."""
+    import torch
+    key = (width, height, tile, frac, seed, str(device))
+    hit = _probe_cache.get(key)
+    if hit is None:
+        mask_t, mask = probe_mask(width, height, tile, frac, seed, device)
+        rows = np.repeat(np.repeat(mask, tile, 0), tile, 1)[:height, :width]
+        idx = torch.from_numpy(np.flatnonzero(rows)).to(device)
+        hit = (mask_t, mask, idx)
+        _probe_cache[key] = hit
+    return hit
+
+
+_side_streams = {}
+
+
+def _side_stream(device):
+    import torch
+    key = str(device)
+    if key not in _side_streams:
+        _side_streams[key] = torch.cuda.Stream(device=device)  # default priority
+    return _side_streams[key]
+
+
 def render_learned(parts_full, parts_dec, cam, palette, species, recon: Reconstructor, *,
                    threshold_db=40.0, probe_frac=0.02, seed=0, tile=16, **kw):
     """Decimated render + reconstruction, checked by a probe: the full set
     rendered on a seeded sample of tiles.  Returns (image, info) where
-    info has the probe PSNR and whether the full render was used instead."""
+    info has the probe PSNR and whether the full render was used instead.
+
+    The probe renders on a side stream while the network runs: it waits
+    only for the decimated render (the two renders share the library's
+    workspace), and the caller's stream waits for it before the PSNR."""
     import torch
+    main = torch.cuda.current_stream()
+    dev = parts_full["x"].device
+    mask_t, mask, idx = _probe_sel(cam.width, cam.height, tile, probe_frac, seed, dev)
+    # sized for the larger of the two renders, allocated on this stream
+    if kw.get("workspace") is None:
+        pk = {k: v for k, v in kw.items() if k in ("sigma_over_h", "trunc_f", "compensated",
+                                                   "accumulate", "seg_records", "splat_variant")}
+        mp = int(kw.get("max_pairs") or 0)
+        B.reserve_workspace(parts_full, cam, species, mp, tile=tile, tile_mask=mask_t, **pk)
+        B.reserve_workspace(parts_dec, cam, species, mp, tile=tile, **pk)
     dec = B.render(parts_dec, cam, palette, species, tile=tile, **kw)
+    dec_done = main.record_event()
+    probe = torch.zeros_like(dec)
     rec = recon.infer(dec)
-    mask_t, mask = probe_mask(cam.width, cam.height, tile, probe_frac, seed, dec.device)
-    probe = torch.zeros_like(rec)
-    B.render(parts_full, cam, palette, species, probe, tile=tile, tile_mask=mask_t, **kw)
-    rows = np.repeat(np.repeat(mask, tile, 0), tile, 1)[:cam.height, :cam.width].astype(bool)
-    sel = torch.from_numpy(rows).to(dec.device)
-    a = rec[:, sel].cpu().numpy()
-    b = probe[:, sel].cpu().numpy()
-    p = psnr_tonemapped(a, b)
+    side = _side_stream(dec.device)
+    side.wait_event(dec_done)
+    with torch.cuda.stream(side):
+        B.render(parts_full, cam, palette, species, probe, tile=tile, tile_mask=mask_t, **kw)
+    main.wait_stream(side)
+    probe.record_stream(side)
+    pair = torch.stack([rec.reshape(3, -1).index_select(1, idx),
+                        probe.reshape(3, -1).index_select(1, idx)]).cpu().numpy()
+    p = psnr_tonemapped(pair[0], pair[1])
     info = dict(probe_psnr=p, fallback=bool(p < threshold_db), probe_tiles=int(mask.sum()))
     if info["fallback"]:
         return B.render(parts_full, cam, palette, species, tile=tile, **kw), info

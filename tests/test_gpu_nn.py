@@ -98,6 +98,29 @@ def test_fused_conv3x3(torch, n, h, w, ci, co, relu, res):
     assert np.array_equal(gb, R.bf16(got.astype(np.float64)))
 
 
+def test_pool_and_upsample_concat_exact(torch):
+    """The 2x2 average pool (FP32 sum in a fixed order, one rounding to
+    BF16) and the nearest upsample + channel concat (a copy) are exact."""
+    rng = np.random.default_rng(21)
+    ops = LN.Ops()
+    n, h, w, c = 2, 6, 10, 40
+    xb, x64 = to_bf16_bits(torch, rng.standard_normal((n * h * w, c)))
+    out = torch.empty((n * (h // 2) * (w // 2), c), dtype=torch.int16, device="cuda")
+    ops.pool2(xb, out, n, h, w, c)
+    x = x64.reshape(n, h, w, c).astype(np.float32)
+    sm = ((x[:, 0::2, 0::2] + x[:, 0::2, 1::2]) + x[:, 1::2, 0::2]) + x[:, 1::2, 1::2]
+    ref = R.bf16((np.float32(0.25) * sm).astype(np.float64))
+    assert np.array_equal(bits_to_f64(out).reshape(ref.shape), ref)
+    ca, cs = 24, 40
+    ab, a64 = to_bf16_bits(torch, rng.standard_normal((n * (h // 2) * (w // 2), ca)))
+    sb, s64 = to_bf16_bits(torch, rng.standard_normal((n * h * w, cs)))
+    cat = torch.empty((n * h * w, ca + cs), dtype=torch.int16, device="cuda")
+    ops.up2_concat(ab, ca, sb, cs, cat, n, h, w)
+    up = np.repeat(np.repeat(a64.reshape(n, h // 2, w // 2, ca), 2, 1), 2, 2)
+    ref = np.concatenate([up, s64.reshape(n, h, w, cs)], axis=3)
+    assert np.array_equal(bits_to_f64(cat).reshape(ref.shape), ref)
+
+
 def test_conv_layer_forward_backward(torch):
     rng = np.random.default_rng(5)
     n, h, w, ci, co = 2, 16, 24, 32, 64
@@ -239,6 +262,19 @@ def test_probe_and_fallback(torch):
     img, info = LN.render_learned(parts, dec, cams[0], pal, sc.species_params, rec,
                                   threshold_db=0.0, compensated=True)
     assert not info["fallback"] and info["probe_tiles"] >= 1
+    # the probe (rendered on a side stream while the network runs) against
+    # the same steps one after another on the caller's stream
+    d = B.render(dec, cams[0], pal, sc.species_params, tile=16, compensated=True)
+    r = rec.infer(d)
+    mask_t, mask = LN.probe_mask(128, 128, 16, 0.02, 0, "cuda")
+    probe = torch.zeros_like(r)
+    B.render(parts, cams[0], pal, sc.species_params, probe, tile=16, tile_mask=mask_t,
+             compensated=True)
+    torch.cuda.synchronize()
+    sel = np.repeat(np.repeat(mask, 16, 0), 16, 1).astype(bool)
+    p_serial = LN.psnr_tonemapped(r.cpu().numpy()[:, sel], probe.cpu().numpy()[:, sel])
+    assert info["probe_psnr"] == p_serial
+    assert np.array_equal(img.cpu().numpy(), r.cpu().numpy())
     img2, info2 = LN.render_learned(parts, dec, cams[0], pal, sc.species_params, rec,
                                     threshold_db=1e9, compensated=True)
     assert info2["fallback"]
