@@ -351,10 +351,10 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 // 8x8 block of the tile and streams the item's list on its own, with no
 // barrier between waves (waves whose blocks see fewer records do not wait
 // for the others).  Pair keys carry, above the tile index, the mask of the
-// tile's blocks that the particle's box meets: the wave scans keys 256 at
-// a time and queues, in list order, the particle indices of the pairs
-// whose mask holds its block, so it gathers and expands only those.  Up to
-// 64 queued records at a time are staged in the wave's own LDS rows,
+// tile's blocks that the particle's box meets: the wave scans keys 64 at a
+// time and queues, in list order, the particle indices of the pairs whose
+// mask holds its block, so it gathers and expands only those.  Up to 64
+// queued records at a time are staged in the wave's own LDS rows,
 // 64 bytes per record, read back as four broadcast 16-byte rows:
 //   {u - i0, v - j0, r^2, log2(e)/sigma^2}, {2 i0, 2 j0, 2 (i1 - i0) + 1,
 //   2 (j1 - j0) + 1} as floats, {E c rho0, flags}, {A c rho0, 0}.
@@ -369,8 +369,12 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;  // 8x8 blocks per tile, one workgroup of one wave each
     constexpr int QW = T / 8;    // blocks per tile row
-    constexpr uint32_t kQ = 512;  // queue ring: < 64 left over + 256 scanned
-    __shared__ float4 s_r[4][64];
+    constexpr uint32_t kB = 64;   // records staged per batch (one per lane)
+    constexpr int kS = 1;         // 64-key chunks per scan
+    constexpr uint32_t kQ = 128;  // queue ring: < kB left over + 64 kS scanned
+    static_assert(kB <= 64, "one record per lane");
+    static_assert(kB - 1 + 64 * kS <= kQ && (kQ & (kQ - 1)) == 0, "queue ring");
+    __shared__ float4 s_r[4][kB];
     __shared__ uint32_t s_q[kQ];
     __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
 
@@ -404,16 +408,16 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
     float T0 = 1.f, T1 = 1.f, T2 = 1.f;
 
-    // Keys and values of the next 256 positions are loaded one scan ahead,
+    // Keys and values of the next 64 kS positions are loaded one scan ahead,
     // at positions clamped to the segment's last pair (always valid).
     const bool masked = a.qshift != 0;
     const uint32_t bit = masked ? (uint32_t)a.qshift + sub : 0u;
     const uint32_t last = end > start ? end - 1 : start;
-    uint32_t kq[4] = {0u, 0u, 0u, 0u}, vq[4] = {0u, 0u, 0u, 0u};
+    uint32_t kq[kS] = {}, vq[kS] = {};
     uint32_t pos = start;
     auto load_scan = [&](uint32_t p) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < kS; ++c) {
             const uint32_t q = p + 64 * c + lane;
             const uint32_t qc = q < last ? q : last;
             if (masked) kq[c] = a.pair_key[qc];
@@ -422,15 +426,15 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     };
     uint32_t head = 0, qn = 0;  // queue ring: entries [head, head + qn)
     auto fill = [&]() {
-        while (qn < 64 && pos < end) {
+        while (qn < kB && pos < end) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < kS; ++c) {
                 const bool hit = pos + 64 * c + lane < end && (!masked || ((kq[c] >> bit) & 1u));
                 const uint64_t m = __ballot(hit);
                 if (hit) s_q[(head + qn + __popcll(m & below)) & (kQ - 1)] = vq[c];
                 qn += (uint32_t)__popcll(m);
             }
-            pos += 256;
+            pos += 64 * kS;
             if (pos < end) load_scan(pos);
         }
     };
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
         head += n;
         qn -= n;
     };
-    uint32_t ncur = qn < 64 ? qn : 64;
+    uint32_t ncur = qn < kB ? qn : kB;
     gather(ncur);
     while (ncur > 0) {
         if ((uint32_t)lane < ncur) {
@@ -463,7 +467,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             s_r[3][lane] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
         }
         fill();
-        const uint32_t nnext = qn < 64 ? qn : 64;
+        const uint32_t nnext = qn < kB ? qn : kB;
         gather(nnext);
         // the wave reads back its own rows (a wave's LDS requests complete
         // in order)
