@@ -177,7 +177,7 @@ constexpr int kSplatBox = 0, kSplatRows = 1, kSplatLists = 2;
 // Segment length rule (shared by host and device): a multiple of the
 // staging batch nt, at least seg_min, and at least pairs / kSegTarget so
 // that a pass has at most n_tiles + kSegTarget items.
-constexpr uint64_t kSegTarget = 8192;
+constexpr uint64_t kSegTarget = 65536;
 __host__ __device__ inline uint32_t seg_len_rule(uint64_t npairs, uint32_t nt, uint32_t seg_min) {
     uint64_t s = (npairs + kSegTarget - 1) / kSegTarget;
     if (s < seg_min) s = seg_min;

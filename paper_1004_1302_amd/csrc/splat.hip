@@ -114,7 +114,7 @@ __device__ __forceinline__ void composite(bool emit_only, float w, float e0, flo
     }
 }
 
-constexpr uint32_t kRun = 8;  // consecutive items per XCD run
+constexpr uint32_t kRun = 2;  // consecutive items per XCD run
 
 // Final pixel value: composite over the incoming image when accumulating.
 template <bool ORDERED>

@@ -75,7 +75,10 @@ def test_workspace_size_monotone():
     assert _ws_size(-1, cam, prm)[0] == 1
 
 
-def _seg_len_rule(npairs, nt, seg_min, target=8192):
+SEG_TARGET = 65536  # kSegTarget of the library
+
+
+def _seg_len_rule(npairs, nt, seg_min, target=SEG_TARGET):
     s = max(-(-npairs // target), seg_min)
     return -(-s // nt) * nt
 
@@ -83,8 +86,8 @@ def _seg_len_rule(npairs, nt, seg_min, target=8192):
 def test_segment_slot_bound():
     """A tile of L > s records is cut into ceil(L/s) < 2L/s segments, so a
     pass with P pairs fills fewer than 2P/s partial slots; with s at least
-    the segment minimum and at least P/8192, that is at most
-    2 min(8192, P/seg_min).  Checked on skewed tile-length mixes, and the
+    the segment minimum and at least P/65536, that is at most
+    2 min(65536, P/seg_min).  Checked on skewed tile-length mixes, and the
     workspace grows when a shorter segment minimum needs more slots."""
     rng = np.random.default_rng(0)
     for trial in range(3000):
@@ -96,8 +99,8 @@ def test_segment_slot_bound():
         P = int(L.sum())
         s = _seg_len_rule(P, nt, seg_min)
         nseg = np.where(L == 0, 1, -(-L // s))
-        assert nseg[nseg > 1].sum() <= min(2 * 8192, 2 * (P // seg_min) + 2)
-        assert nseg.sum() <= L.size + 8192
+        assert nseg[nseg > 1].sum() <= min(2 * SEG_TARGET, 2 * (P // seg_min) + 2)
+        assert nseg.sum() <= L.size + SEG_TARGET
     cam = B.camera_struct(synth.ortho_unit_square(256, 256))
     short, default = _params(seg_records=256), _params()
     assert _ws_size(1000, cam, short, 10 ** 6)[1] > _ws_size(1000, cam, default, 10 ** 6)[1]
