@@ -62,15 +62,19 @@ __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
 // Scan inputs: plain values, or tile counts decoded from a tagged
 // processing order (see radix_sort_pairs).
+// A load is split in two steps, raw() and finish(), so that a workgroup
+// issues all of its streaming loads before the rare dependent ones.
 template <typename TI>
 struct LoadPlain {
     const TI *p;
-    __device__ __forceinline__ TI operator()(size_t i) const { return p[i]; }
+    __device__ __forceinline__ TI raw(size_t i) const { return p[i]; }
+    __device__ __forceinline__ TI finish(TI r) const { return r; }
 };
 struct LoadTaggedCount {
     const uint32_t *order, *cnt;
-    __device__ __forceinline__ uint32_t operator()(size_t i) const {
-        const uint32_t v = order[i], code = v >> kTagShift;
+    __device__ __forceinline__ uint32_t raw(size_t i) const { return order[i]; }
+    __device__ __forceinline__ uint32_t finish(uint32_t v) const {
+        const uint32_t code = v >> kTagShift;
         return code == 0 ? cnt[v & kIdxMask] : (code == 3 ? 4u : code);
     }
 };
@@ -79,11 +83,17 @@ template <typename L, typename TO>
 __global__ __launch_bounds__(kT) void k_scan_reduce(L in, size_t n, TO *partial) {
     __shared__ TO s_w[kW];
     const size_t base = (size_t)blockIdx.x * kTile;
+    decltype(in.raw(0)) r[kIpt];
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        size_t idx = base + (size_t)q * kT + threadIdx.x;
+        if (idx < n) r[q] = in.raw(idx);
+    }
     TO s = 0;
 #pragma unroll
     for (int q = 0; q < kIpt; ++q) {
         size_t idx = base + (size_t)q * kT + threadIdx.x;
-        if (idx < n) s += (TO)in(idx);
+        if (idx < n) s += (TO)in.finish(r[q]);
     }
     TO tot;
     block_excl_scan<kW>(s, s_w, &tot);
@@ -110,11 +120,17 @@ __global__ __launch_bounds__(kT) void k_scan_down(L in, TO *out, size_t n, const
     __shared__ TO s[kTile + kTile / 16];
     __shared__ TO s_w[kW];
     const size_t base = (size_t)blockIdx.x * kTile;
+    decltype(in.raw(0)) r[kIpt];
+#pragma unroll
+    for (int q = 0; q < kIpt; ++q) {
+        size_t idx = base + (size_t)q * kT + threadIdx.x;
+        if (idx < n) r[q] = in.raw(idx);
+    }
 #pragma unroll
     for (int q = 0; q < kIpt; ++q) {
         int l = q * kT + threadIdx.x;
         size_t idx = base + l;
-        s[pad(l)] = idx < n ? (TO)in(idx) : (TO)0;
+        s[pad(l)] = idx < n ? (TO)in.finish(r[q]) : (TO)0;
     }
     __syncthreads();
     TO v[kIpt];
