@@ -150,12 +150,15 @@ typedef struct splotch_params {
     int32_t profile;     /* 1: time each stage (needs stats) */
     int32_t seg_records; /* least records per tile-list segment (one workgroup
                             each); 0 = 1024.  Long lists are cut into segments
-                            merged front to back; this only affects speed. */
+                            whose partial (C, T) are merged front to back:
+                            this changes speed and, within rounding, how a
+                            tile's sums are associated. */
     int32_t splat_variant; /* how a tile's list is walked (speed only, the
                             image is the same):
                             0 = default (1);
-                            1 = one lane per pixel: every wave tests each
-                                record against its pixel rows;
+                            1 = one lane per pixel: the wave of each 8x8
+                                block walks the records whose box meets
+                                its block;
                             2 = one lane per pixel: each lane first lists
                                 its member records, then composites them;
                             3 = one wave per tile, pixel state in LDS, the
