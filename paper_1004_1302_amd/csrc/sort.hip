@@ -202,17 +202,21 @@ __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_c
     for (int d = threadIdx.x; d < kHistCopies * 256; d += kT) (&sh[0][0])[d] = 0;
     __syncthreads();
     const int c = threadIdx.x & (kHistCopies - 1);
-    const size_t base = (size_t)blockIdx.x * kTile;
+    // contiguous tile ranges per XCD, as in k_rs_scatter: neighbouring
+    // tiles' counts share lines of the digit-major histogram
+    const uint32_t q8 = nblocks / 8, r8 = nblocks % 8, x8 = blockIdx.x % 8;
+    const uint32_t t = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+    const size_t base = (size_t)t * kTile;
 #pragma unroll
     for (int q = 0; q < kIpt; ++q) {
         size_t idx = base + (size_t)q * kT + threadIdx.x;
         if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & 255u], 1u);
     }
     __syncthreads();
-    uint32_t t = 0;
+    uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kHistCopies; ++k) t += sh[k][threadIdx.x];
-    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = t;
+    for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
+    hist[(size_t)threadIdx.x * nblocks + t] = sum;
 }
 
 __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
@@ -222,12 +226,18 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
                                                    uint32_t nblocks, int write_keys,
                                                    const uint32_t *tag) {
     const size_t n = live_count(n_cap, n_dev);
-    if ((size_t)blockIdx.x * kTile >= n) return;  // whole block past the live count
+    // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
+    // contiguous range of tiles, so that the runs two neighbouring tiles
+    // write for one digit (adjacent in the output) meet in one L2 instead
+    // of leaving two partial lines in two.  A bijection on [0, nblocks).
+    const uint32_t q8 = nblocks / 8, r8 = nblocks % 8, x8 = blockIdx.x % 8;
+    const uint32_t t = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+    if ((size_t)t * kTile >= n) return;  // whole block past the live count
     __shared__ uint32_t s_k[kTile], s_v[kTile];
     __shared__ uint32_t s_wc[kW][256];
     __shared__ uint32_t s_bs[256], s_go[256], s_sw[kW];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const size_t base = (size_t)blockIdx.x * kTile;
+    const size_t base = (size_t)t * kTile;
     for (int d = tid; d < kW * 256; d += kT) (&s_wc[0][0])[d] = 0;
     // dg: the key's digit; entries past the live count take digit 255 so
     // that they rank after every live entry of the tile
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
     s_bs[tid] = ex;
 #pragma unroll
     for (int ww = 0; ww < kW; ++ww) s_wc[ww][tid] = wpre[ww];
-    s_go[tid] = hist[(size_t)tid * nblocks + blockIdx.x];
+    s_go[tid] = hist[(size_t)tid * nblocks + t];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
