@@ -65,6 +65,16 @@ struct ProjectArgs {
     uint32_t *o_key;
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin.  This maps workgroup b
+// of nblocks to the chunk it processes so that each XCD gets a contiguous
+// range of chunks: outputs of neighbouring chunks that share cache lines
+// then meet in one XCD's L2 instead of leaving partial lines in two.  A
+// bijection on [0, nblocks).
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nblocks) {
+    const uint32_t q = nblocks / 8, r = nblocks % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
 // ---- launchers (one per kernel family) ------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, size_t n, hipStream_t s);

@@ -202,10 +202,8 @@ __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_c
     for (int d = threadIdx.x; d < kHistCopies * 256; d += kT) (&sh[0][0])[d] = 0;
     __syncthreads();
     const int c = threadIdx.x & (kHistCopies - 1);
-    // contiguous tile ranges per XCD, as in k_rs_scatter: neighbouring
-    // tiles' counts share lines of the digit-major histogram
-    const uint32_t q8 = nblocks / 8, r8 = nblocks % 8, x8 = blockIdx.x % 8;
-    const uint32_t t = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+    // neighbouring tiles' counts share lines of the digit-major histogram
+    const uint32_t t = xcd_contiguous(blockIdx.x, nblocks);
     const size_t base = (size_t)t * kTile;
 #pragma unroll
     for (int q = 0; q < kIpt; ++q) {
@@ -226,12 +224,9 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
                                                    uint32_t nblocks, int write_keys,
                                                    const uint32_t *tag) {
     const size_t n = live_count(n_cap, n_dev);
-    // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-    // contiguous range of tiles, so that the runs two neighbouring tiles
-    // write for one digit (adjacent in the output) meet in one L2 instead
-    // of leaving two partial lines in two.  A bijection on [0, nblocks).
-    const uint32_t q8 = nblocks / 8, r8 = nblocks % 8, x8 = blockIdx.x % 8;
-    const uint32_t t = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+    // the runs two neighbouring tiles write for one digit are adjacent in
+    // the output
+    const uint32_t t = xcd_contiguous(blockIdx.x, nblocks);
     if ((size_t)t * kTile >= n) return;  // whole block past the live count
     __shared__ uint32_t s_k[kTile], s_v[kTile];
     __shared__ uint32_t s_wc[kW][256];
