@@ -56,6 +56,48 @@ def test_batch_matches_single_views(scene, orc):
     assert np.all(rel <= 1e-4), rel
 
 
+def test_batch_at_the_batched_views_sizes(scene, orc):
+    """The batched-views workload's shape at a reduced particle count:
+    cameras on the seeded orbit at 512², 1024², 1920x1080 and 2048², one
+    batch on four streams captured as a graph, every view bit-identical to
+    its single render; the 2048² view against the oracle on sampled pixels
+    (the 64 brightest and 192 random ones)."""
+    import torch
+    parts, pal = B.scene_to_device(scene)
+    sizes = [(512, 512), (1024, 1024), (1920, 1080), (2048, 2048)]
+    cams = orbit_cameras(8, 11, sizes)
+    cams[-1] = orbit_cameras(1, 12, [(2048, 2048)])[0]
+    # room for every view's pairs (the 2048² views bin about 4.5 per
+    # particle), so that no render here is cut into depth slabs
+    mp = 1 << 23
+    refs = [single(parts, c, pal, scene.species_params, max_pairs=mp) for c in cams]
+    _, st = B.render_batch(parts, cams, pal, scene.species_params, compensated=True,
+                           streams=4, max_pairs=mp, stats=True)
+    assert all(s["n_chunks"] == 1 and s["n_pairs"] > 0 for s in st)
+    B.graph_cache_clear()
+    images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device="cuda")
+              for c in cams]
+    for rep in range(2):
+        out = B.render_batch(parts, cams, pal, scene.species_params, images, graph=True,
+                             compensated=True, streams=4, max_pairs=mp)
+        torch.cuda.synchronize()
+        for v in range(len(cams)):
+            assert np.array_equal(out[v].cpu().numpy(), refs[v]), f"replay {rep} view {v}"
+    B.graph_cache_clear()
+    cam = cams[-1]
+    got = refs[-1].astype(np.float64)
+    lum = got.sum(0).ravel()
+    rng = np.random.default_rng(13)
+    pick = np.concatenate([np.argsort(lum)[-64:], rng.integers(0, lum.size, 192)])
+    pj, pi = np.divmod(pick, cam.width)
+    sc = synth.Scene(scene.x, scene.y, scene.z, scene.h, scene.value, cam,
+                     scene.species_params, species=scene.species)
+    o = orc.render_pixels(sc, pi.astype(np.int32), pj.astype(np.int32)).T
+    g = got.reshape(3, -1)[:, pick]
+    rel = np.abs(g - o).max(1) / np.abs(o).max(1)
+    assert np.all(rel <= 1e-4), rel
+
+
 @pytest.mark.parametrize("streams", [2, 3, 4])
 def test_batch_on_several_streams_matches_single_views(scene, streams):
     """Views round-robin over several streams (each with its own workspace
