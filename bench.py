@@ -126,6 +126,7 @@ def main():
     ap.add_argument("--workload", default="lognormal",
                     choices=["lognormal", "nfw", "plummer", "learned", "batch"])
     ap.add_argument("--views", type=int, default=32)
+    ap.add_argument("--batch-set", default="nfw", choices=["nfw", "plummer"])
     ap.add_argument("--train-pairs", type=int, default=2000)
     ap.add_argument("--test-views", type=int, default=20)
     ap.add_argument("--size", type=int, default=1024)
@@ -252,18 +253,29 @@ def batch_leg(args, np, torch):
     from paper_1004_1302_amd import autotune
     from paper_1004_1302_amd import binding as B
     from paper_1004_1302_amd import synth
-    n = int(args.n or 10_000_000)
-    sc = synth.nfw_halos(n, seed=2)
+    if args.batch_set == "plummer":
+        # the batched-views workload: the small-config generator (one
+        # additive species) on the unit-cube orbit, 512² to 2048² views
+        n = int(args.n or 50_000_000)
+        sc = synth.plummer_mix(n, seed=41)
+        sizes = [(512, 512), (1024, 1024), (1920, 1080), (2048, 2048)]
+        cams = synth.orbit_cameras(args.views, 7, sizes)
+        name = "plummer_mix_multiview"
+    else:
+        n = int(args.n or 10_000_000)
+        sc = synth.nfw_halos(n, seed=2)
+        # light sets use thumbnail sizes, where launch overhead is a large share
+        sizes = ([(1920, 1080), (1280, 720), (1024, 1024), (640, 480)] if n > 1_000_000 else
+                 [(320, 240), (256, 256), (200, 150), (128, 128)])
+        cams = synth.orbit_cameras(args.views, 7, sizes, centre=(50.0, 50.0, 50.0),
+                                   radius=150.0, z_near=1.0, z_far=1000.0)
+        name = "nfw_halos_multiview"
     parts, pal = B.scene_to_device(sc, "cuda:0")
     sp = sc.species_params
-    # light sets use thumbnail sizes, where launch overhead is a large share
-    sizes = ([(1920, 1080), (1280, 720), (1024, 1024), (640, 480)] if n > 1_000_000 else
-             [(320, 240), (256, 256), (200, 150), (128, 128)])
-    cams = synth.orbit_cameras(args.views, 7, sizes, centre=(50.0, 50.0, 50.0), radius=150.0,
-                               z_near=1.0, z_far=1000.0)
     tuned = autotune.tune(parts, cams[0], pal, sp, use_cache=False, compensated=True)
     log(f"autotune: tile {tuned['tile']} seg_records {tuned['seg_records']}")
-    kw = dict(compensated=True, tile=tuned["tile"], seg_records=tuned["seg_records"])
+    kw = dict(compensated=True, tile=tuned["tile"], seg_records=tuned["seg_records"],
+              max_pairs=int(args.max_pairs or 0))
     images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device="cuda:0")
               for c in cams]
     px = sum(c.width * c.height for c in cams)
@@ -284,6 +296,10 @@ def batch_leg(args, np, torch):
         for c, im in zip(cams, images):
             B.render(parts, c, pal, sp, im, **kw)
 
+    # one checked batch first: a view whose pairs exceed the capacity raises
+    _, st = B.render_batch(parts, cams, pal, sp, images, stats=True, streams=4, **kw)
+    log(f"batch: most pairs in a view {max(v['n_pairs'] for v in st)}, "
+        f"chunks {max(v['n_chunks'] for v in st)}")
     reps = max(3, args.steps)
     ms_single = timed(singles, reps)
     ms_batch = timed(lambda: B.render_batch(parts, cams, pal, sp, images, **kw), reps)
@@ -303,7 +319,7 @@ def batch_leg(args, np, torch):
         "n_gpus": 1,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict(workload="nfw_halos_multiview", n_particles=n, views=len(cams),
+        "config": dict(workload=name, n_particles=n, views=len(cams),
                        sizes=sizes, pixels_per_batch=px, tile=tuned["tile"],
                        seg_records=tuned["seg_records"], compensated=True),
         "ms_per_batch_single_calls": round(ms_single, 3),
