@@ -473,9 +473,15 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
         // in order)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // each visit reads the next record's rows before working on its
+        // own, so no visit waits on the LDS for its rows
+        float4 fn = s_r[0][0], gn = s_r[1][0], en = s_r[2][0];
         auto visit = [&](uint32_t r) {
-            const float4 g = s_r[1][r];
-            const float4 f = s_r[0][r];
+            const float4 f = fn, g = gn, e = en;
+            const uint32_t rn = r + 1 < ncur ? r + 1 : r;
+            fn = s_r[0][rn];
+            gn = s_r[1][rn];
+            en = s_r[2][rn];
             const float ax = tfx - g.x, ay = tfy - g.y;
             float d2;
             {
@@ -487,7 +493,6 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             // no short-circuit: one mask, no branch around the comparisons
             const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
             if (__ballot(in) == 0ull) return;
-            const float4 e = s_r[2][r];
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
             if (!in) return;
