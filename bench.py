@@ -241,12 +241,16 @@ def main():
 
 
 def batch_leg(args, np, torch):
-    """Many views of one device-resident particle set: the NFW halo set
-    (--n particles, default 1e7, mixed ordered species), --views cameras on
-    a seeded orbit, each of one of four sizes (1920x1080, 1280x720,
-    1024x1024, 640x480; for 1e6 particles or fewer 320x240, 256x256,
-    200x150, 128x128).  The autotuner picks tile and segment length on the first
-    view.  Timed: one render call per view, one batch call (eager), and
+    """Many views of one device-resident particle set.  --batch-set nfw: the
+    NFW halo set (--n particles, default 1e7, mixed ordered species),
+    --views cameras on a seeded orbit, each of one of four sizes (1920x1080,
+    1280x720, 1024x1024, 640x480; for 1e6 particles or fewer 320x240,
+    256x256, 200x150, 128x128).  --batch-set plummer: the batched-views
+    workload, the small-config generator (default 5e7 particles, additive)
+    seen from the unit-cube orbit at 512², 1024², 1920x1080 and 2048² (pass
+    --max-pairs for the largest views).  The autotuner picks tile and
+    segment length on the first view; one checked batch (stats on) runs
+    before timing.  Timed: one render call per view, one batch call (eager), and
     replays of the batch captured as a HIP graph, each on one stream and on
     four; wall clock per batch with the device synchronised on both
     sides.  `value` is the fastest batch mode's views/s."""
