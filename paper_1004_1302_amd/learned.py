@@ -516,10 +516,13 @@ def _side_stream(device):
 
 
 def render_learned(parts_full, parts_dec, cam, palette, species, recon: Reconstructor, *,
-                   threshold_db=40.0, probe_frac=0.02, seed=0, tile=16, **kw):
+                   threshold_db=40.0, probe_frac=0.02, seed=0, tile=16, dec_tile=32, **kw):
     """Decimated render + reconstruction, checked by a probe: the full set
-    rendered on a seeded sample of tiles.  Returns (image, info) where
-    info has the probe PSNR and whether the full render was used instead.
+    rendered on a seeded sample of tiles (of `tile` px).  Returns (image,
+    info) where info has the probe PSNR and whether the full render was used
+    instead.  The decimated render uses tiles of `dec_tile` px: its
+    footprints are 16^(1/3) times wider, and 32 px tiles render them fastest
+    (1.21 ms against 1.60 at 16 px for 1.25e6 particles at 1024²).
 
     The probe renders on a side stream while the network runs: it waits
     only for the decimated render (the two renders share the library's
@@ -534,8 +537,8 @@ def render_learned(parts_full, parts_dec, cam, palette, species, recon: Reconstr
                                                    "accumulate", "seg_records", "splat_variant")}
         mp = int(kw.get("max_pairs") or 0)
         B.reserve_workspace(parts_full, cam, species, mp, tile=tile, tile_mask=mask_t, **pk)
-        B.reserve_workspace(parts_dec, cam, species, mp, tile=tile, **pk)
-    dec = B.render(parts_dec, cam, palette, species, tile=tile, **kw)
+        B.reserve_workspace(parts_dec, cam, species, mp, tile=dec_tile, **pk)
+    dec = B.render(parts_dec, cam, palette, species, tile=dec_tile, **kw)
     dec_done = main.record_event()
     probe = torch.zeros_like(dec)
     rec = recon.infer(dec)

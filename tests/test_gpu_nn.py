@@ -264,7 +264,7 @@ def test_probe_and_fallback(torch):
     assert not info["fallback"] and info["probe_tiles"] >= 1
     # the probe (rendered on a side stream while the network runs) against
     # the same steps one after another on the caller's stream
-    d = B.render(dec, cams[0], pal, sc.species_params, tile=16, compensated=True)
+    d = B.render(dec, cams[0], pal, sc.species_params, tile=32, compensated=True)
     r = rec.infer(d)
     mask_t, mask = LN.probe_mask(128, 128, 16, 0.02, 0, "cuda")
     probe = torch.zeros_like(r)
