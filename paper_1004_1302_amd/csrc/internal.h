@@ -181,6 +181,7 @@ struct SplatArgs {
     int width, height, tile, ntx, nty;
     int accumulate, compensated, ordered;
     int variant;  // kSplatBox, kSplatRows or kSplatLists (see splat.hip)
+    int count;    // 1: accumulate the member statistics (the row walk skips them otherwise)
 };
 // How a workgroup walks a tile's list.
 constexpr int kSplatBox = 0, kSplatRows = 1, kSplatLists = 2;

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 // (exact), a in [1, 2 (i1 - i0) + 1] is the box test and
 // fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0) once, which is
 // the binary32 offset of the index recipe bit for bit.
-template <int T, bool ORDERED, bool KAHAN>
+template <int T, bool ORDERED, bool KAHAN, bool COUNT>
 __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;  // 8x8 blocks per tile, one workgroup of one wave each
@@ -496,13 +496,13 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
             const bool emit_only = (flags & kEmitOnly) != 0;
             if (!in) return;
-            ++n_member;
+            if (COUNT) ++n_member;
             const float w = __builtin_amdgcn_exp2f(-d2 * f.w);  // exp(-q^2)
             if (!ORDERED || emit_only) {
                 composite<ORDERED, KAHAN>(true, w, e.x, e.y, e.z, 0.f, 0.f, 0.f, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
             } else {
-                ++n_absorb;
+                if (COUNT) ++n_absorb;
                 // E = A: the emission row doubles as the absorption row
                 const float4 x = s_r[(flags & kEmitEqAbsorb) ? 2 : 3][r];
                 composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
@@ -525,11 +525,13 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         ncur = nnext;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        n_member += __shfl_xor(n_member, o, 64);
-        n_absorb += __shfl_xor(n_absorb, o, 64);
+    if (COUNT) {
+        for (int o = 32; o > 0; o >>= 1) {
+            n_member += __shfl_xor(n_member, o, 64);
+            n_absorb += __shfl_xor(n_absorb, o, 64);
+        }
     }
-    if (lane == 0) {
+    if (COUNT && lane == 0) {
         // statistics only; compositing itself uses no atomics
         if (n_member) atomicAdd(&a.member_count[2 * tile], (unsigned long long)n_member);
         if (n_absorb) atomicAdd(&a.member_count[2 * tile + 1], (unsigned long long)n_absorb);
@@ -782,8 +784,12 @@ hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     switch (a.variant) {
         case kSplatRows:
             // one single-wave workgroup per 8x8 block of every item
-            hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN>), dim3(grid * (T * T / 64)),
-                               dim3(64), 0, s, a);
+            if (a.count)
+                hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true>),
+                                   dim3(grid * (T * T / 64)), dim3(64), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false>),
+                                   dim3(grid * (T * T / 64)), dim3(64), 0, s, a);
             break;
         case kSplatLists:
             hipLaunchKernelGGL((k_splat_lists<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
