@@ -828,7 +828,8 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.max_items = c.L.max_items;
     sa.seg_len = c.at<uint32_t>(c.L.seg_len);
     sa.qshift = block_mask_shift(c.L.tile, c.L.n_tiles);
-    sa.count = p->stats != nullptr ? 1 : 0;  // member statistics only when asked for
+    // member statistics only where they are reported (profiled stats)
+    sa.count = (p->stats != nullptr && p->profile != 0) ? 1 : 0;
     TRY(launch_fill_u32(c.at<uint32_t>(c.L.mcount), 0u, (size_t)c.L.n_tiles * 4, c.s));
 
     const uint64_t total = plan.back();

@@ -252,6 +252,17 @@ def test_box_mapped_lanes_chunked(torch_cuda, orc):
     check_image(img, orc.render(scene))
 
 
+def test_statistics_do_not_change_the_image(torch_cuda):
+    """Frames that do not report member statistics (they are reported with
+    profiled stats) run the row walk without its member counters; the image
+    is the same bits either way."""
+    scene = c2_small(60_000, seed=9, w=320, h=200)
+    plain = gpu_render(scene, compensated=True)
+    counted, st = gpu_render(scene, compensated=True, profile=True)
+    assert np.array_equal(plain, counted)
+    assert st["n_member_pairs"] > 0 and 0 < st["n_member_absorbing"] < st["n_member_pairs"]
+
+
 def test_block_masks_on_and_off_bitwise_equal(torch_cuda):
     """Pair keys carry the mask of the tile's 8x8 blocks a footprint meets
     when the tile index leaves room above the sort's digits: 16 px tiles
