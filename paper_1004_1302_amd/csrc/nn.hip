@@ -551,7 +551,9 @@ hipError_t conv3x3(const bf16_t *x, const bf16_t *wf, const float *bias, int rel
                    const float *residual, bf16_t *out_bf, float *out_f, int n, int h, int w,
                    int cin, int cout, hipStream_t s) {
     const unsigned tiles = (unsigned)((h + kCTH - 1) / kCTH) * (unsigned)((w + kCTW - 1) / kCTW);
-    if (cout % 64 == 0) {
+    // 64 output channels per workgroup where that still gives the GPU
+    // enough workgroups, 32 on the small deep levels
+    if (cout % 64 == 0 && (uint64_t)tiles * (uint64_t)n * (uint64_t)(cout / 64) >= 1024) {
         hipLaunchKernelGGL(k_conv3x3<64>, dim3(tiles * (unsigned)n, (unsigned)(cout / 64)),
                            dim3(256), 0, s, x, wf, bias, relu, residual, out_bf, out_f, h, w, cin,
                            cout);
