@@ -57,26 +57,43 @@ P = C.c_void_p
 I64 = C.c_int64
 I32 = C.c_int
 F32 = C.c_float
+MAXS = 8
+
+
+class OrcParticles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", P), ("y", P), ("z", P), ("h", P), ("value", P),
+                ("rho0", P), ("value_g", P), ("value_b", P), ("species", P)]
+
+
+class OrcSettings(C.Structure):
+    _fields_ = [("ns", C.c_int), ("vmin", C.c_float * MAXS), ("vmax", C.c_float * MAXS),
+                ("bright", C.c_float * MAXS), ("absorb", C.c_float * MAXS),
+                ("log_scale", C.c_int * MAXS), ("mode", C.c_int * MAXS),
+                ("colour", C.c_int * MAXS), ("sigma_over_h", C.c_float),
+                ("trunc_f", C.c_float), ("kernel", C.c_int), ("emission_is_source", C.c_int),
+                ("K", C.c_int), ("KA", C.c_int), ("pal", P), ("pal_abs", P)]
 
 
 def _declare(L):
+    PP, PS = C.POINTER(OrcParticles), C.POINTER(OrcSettings)
     L.orc_value_range.restype = None
-    L.orc_value_range.argtypes = [I64, P, P, P, P, P, P, P, I32, P, P, P, P, P]
+    L.orc_value_range.argtypes = [PP, PS, P, P]
     L.orc_normalise.restype = C.c_double
     L.orc_normalise.argtypes = [F32, F32, F32, I32]
     L.orc_palette.restype = None
     L.orc_palette.argtypes = [C.c_double, I32, P, P]
     L.orc_project.restype = None
-    L.orc_project.argtypes = [I64, P, P, P, P, P, P, P, I32, P, I32, I32, I32, F32, F32, I32,
-                              P, P, P, P, P, P]
+    L.orc_project.argtypes = [PP, PS, P, I32, I32, I32, I32, P, P, P, P, P, P]
     L.orc_render.restype = I64
-    L.orc_render.argtypes = [I64, P, P, P, P, P, P, P, I32, P, P, P, P, P, P, P, I32, I32, I32,
-                             F32, F32, I32, P, P, P]
+    L.orc_render.argtypes = [PP, PS, P, I32, I32, I32, P, P]
+    L.orc_render_rows.restype = I64
+    L.orc_render_rows.argtypes = [PP, PS, P, I32, I32, I32, I32, P, P]
+    L.orc_threads.restype = I32
+    L.orc_threads.argtypes = []
     L.orc_render_pixels.restype = I64
-    L.orc_render_pixels.argtypes = [I64, P, P, P, P, P, P, P, I32, P, P, P, P, P, P, P, I32, I32,
-                                    I32, F32, F32, I32, P, I64, P, P, P, P]
+    L.orc_render_pixels.argtypes = [PP, PS, P, I32, I32, I32, I64, P, P, P, P]
     L.orc_raymarch.restype = I32
-    L.orc_raymarch.argtypes = [I64, P, P, P, P, P, P, P, P, I32, I32, F32, F32, I32, P, P]
+    L.orc_raymarch.argtypes = [I64, P, P, P, P, P, P, P, P, I32, I32, F32, F32, I32, I32, P, P]
 
 
 def _p(a):
@@ -94,32 +111,50 @@ def cam_array(cam) -> np.ndarray:
                                     np.float32)]).astype(np.float32)
 
 
-def _species_arrays(sp):
-    ns = len(sp)
-    return dict(
-        ns=ns,
-        vmin=np.array([s.vmin for s in sp], np.float32),
-        vmax=np.array([s.vmax for s in sp], np.float32),
-        log=np.array([s.log_scale for s in sp], np.int32),
-        bright=np.array([s.brightness for s in sp], np.float32),
-        absorb=np.array([s.absorption for s in sp], np.float32),
-        mode=np.array([s.mode for s in sp], np.int32),
-    )
+class _Marshalled:
+    """Particle and settings structs for one scene; keeps the arrays they
+    point to alive."""
 
+    def __init__(self, scene):
+        sp = None if scene.species is None else np.ascontiguousarray(scene.species, np.uint8)
+        self.keep = [_f32(scene.x), _f32(scene.y), _f32(scene.z), _f32(scene.h),
+                     _f32(scene.value), _f32(scene.rho0), _f32(getattr(scene, "value_g", None)),
+                     _f32(getattr(scene, "value_b", None)), sp]
+        x, y, z, h, v, r0, vg, vb, spc = self.keep
+        self.parts = OrcParticles(scene.n, _p(x), _p(y), _p(z), _p(h), _p(v), _p(r0), _p(vg),
+                                  _p(vb), _p(spc))
+        st = OrcSettings()
+        sps = scene.species_params
+        st.ns = len(sps)
+        for k, s in enumerate(sps):
+            st.vmin[k], st.vmax[k] = float(s.vmin), float(s.vmax)
+            st.bright[k], st.absorb[k] = float(s.brightness), float(s.absorption)
+            st.log_scale[k], st.mode[k] = int(s.log_scale), int(s.mode)
+            st.colour[k] = int(getattr(s, "colour", 0))
+            if st.colour[k] == 1 and (vg is None or vb is None):
+                raise ValueError("vector-coloured species need value_g and value_b")
+        st.sigma_over_h, st.trunc_f = float(scene.sigma_over_h), float(scene.trunc_f)
+        st.kernel = int(getattr(scene, "kernel", 0))
+        st.emission_is_source = int(getattr(scene, "emission_is_source", 0))
+        pal = np.ascontiguousarray(scene.palette, np.float32)
+        pa = getattr(scene, "palette_absorb", None)
+        pa = None if pa is None else np.ascontiguousarray(pa, np.float32)
+        self.keep += [pal, pa]
+        st.K, st.pal = pal.shape[0], _p(pal)
+        st.KA, st.pal_abs = (0, None) if pa is None else (pa.shape[0], _p(pa))
+        self.st = st
+        self.cam = cam_array(scene.camera)
 
-def _parts(scene):
-    sp = None if scene.species is None else np.ascontiguousarray(scene.species, dtype=np.uint8)
-    return (_f32(scene.x), _f32(scene.y), _f32(scene.z), _f32(scene.h), _f32(scene.value),
-            _f32(scene.rho0), sp)
+    def args(self):
+        return C.byref(self.parts), C.byref(self.st)
 
 
 def value_range(scene):
-    x, y, z, h, v, r0, sp = _parts(scene)
-    s = _species_arrays(scene.species_params)
-    lo = np.zeros(s["ns"], np.float32)
-    hi = np.zeros(s["ns"], np.float32)
-    lib().orc_value_range(scene.n, _p(x), _p(y), _p(z), _p(h), _p(v), _p(r0), _p(sp), s["ns"],
-                          _p(s["vmin"]), _p(s["vmax"]), _p(s["log"]), _p(lo), _p(hi))
+    m = _Marshalled(scene)
+    ns = m.st.ns
+    lo = np.zeros(ns, np.float32)
+    hi = np.zeros(ns, np.float32)
+    lib().orc_value_range(*m.args(), _p(lo), _p(hi))
     return lo, hi
 
 
@@ -137,64 +172,68 @@ def palette_lookup(t, pal):
 def project(scene, tile=16):
     """Per-particle projection fields (status, bbox, binary32 membership
     fields, depth key, tile count and the exact FP64 u, v, sigma_s, z_c)."""
-    x, y, z, h, v, r0, sp = _parts(scene)
+    m = _Marshalled(scene)
     n = scene.n
     cam = scene.camera
     out = dict(status=np.zeros(n, np.int8), bbox=np.zeros((n, 4), np.int32),
                spec=np.zeros((n, 3), np.float32), key=np.zeros(n, np.uint32),
                ntiles=np.zeros(n, np.uint32), cont=np.zeros((n, 4), np.float64))
-    ca = cam_array(cam)
-    lib().orc_project(n, _p(x), _p(y), _p(z), _p(h), _p(v), _p(r0), _p(sp),
-                      len(scene.species_params), _p(ca), cam.projection, cam.width, cam.height,
-                      scene.sigma_over_h, scene.trunc_f, tile, _p(out["status"]),
-                      _p(out["bbox"]), _p(out["spec"]), _p(out["key"]), _p(out["ntiles"]),
-                      _p(out["cont"]))
+    lib().orc_project(*m.args(), _p(m.cam), cam.projection, cam.width, cam.height, tile,
+                      _p(out["status"]), _p(out["bbox"]), _p(out["spec"]), _p(out["key"]),
+                      _p(out["ntiles"]), _p(out["cont"]))
     return out
 
 
 def render(scene, img_in=None) -> np.ndarray:
-    """FP64 image, planar [3][H][W]."""
-    x, y, z, h, v, r0, sp = _parts(scene)
-    s = _species_arrays(scene.species_params)
+    """FP64 image, planar [3][H][W] (single thread)."""
+    m = _Marshalled(scene)
     cam = scene.camera
-    W, H = cam.width, cam.height
-    pal = np.ascontiguousarray(scene.palette, np.float32)
-    out = np.zeros((3, H, W), np.float64)
+    out = np.zeros((3, cam.height, cam.width), np.float64)
     iin = None if img_in is None else np.ascontiguousarray(img_in, np.float64)
-    ca = cam_array(cam)
-    lib().orc_render(scene.n, _p(x), _p(y), _p(z), _p(h), _p(v), _p(r0), _p(sp), s["ns"],
-                     _p(s["vmin"]), _p(s["vmax"]), _p(s["log"]), _p(s["bright"]),
-                     _p(s["absorb"]), _p(s["mode"]), _p(ca), cam.projection, W, H,
-                     scene.sigma_over_h, scene.trunc_f, pal.shape[0], _p(pal), _p(iin), _p(out))
+    lib().orc_render(*m.args(), _p(m.cam), cam.projection, cam.width, cam.height, _p(iin),
+                     _p(out))
     return out
+
+
+def render_rows(scene, img_in=None, band=16) -> np.ndarray:
+    """The same image as render(), with bands of `band` rows painted in
+    parallel by the OpenMP threads (OMP_NUM_THREADS)."""
+    m = _Marshalled(scene)
+    cam = scene.camera
+    out = np.zeros((3, cam.height, cam.width), np.float64)
+    iin = None if img_in is None else np.ascontiguousarray(img_in, np.float64)
+    lib().orc_render_rows(*m.args(), _p(m.cam), cam.projection, cam.width, cam.height,
+                          int(band), _p(iin), _p(out))
+    return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel parts use."""
+    return int(lib().orc_threads())
 
 
 def render_pixels(scene, pi, pj, in_px=None) -> np.ndarray:
     """FP64 values (npx, 3) at the sample pixels (pi[k], pj[k]).  The scan
     over particles runs on all OpenMP threads; the composite is the same
     for any thread count."""
-    x, y, z, h, v, r0, sp = _parts(scene)
-    s = _species_arrays(scene.species_params)
+    m = _Marshalled(scene)
     cam = scene.camera
-    pal = np.ascontiguousarray(scene.palette, np.float32)
     pi = np.ascontiguousarray(pi, np.int32)
     pj = np.ascontiguousarray(pj, np.int32)
     out = np.zeros((pi.shape[0], 3), np.float64)
     iin = None if in_px is None else np.ascontiguousarray(in_px, np.float64)
-    ca = cam_array(cam)
-    lib().orc_render_pixels(scene.n, _p(x), _p(y), _p(z), _p(h), _p(v), _p(r0), _p(sp), s["ns"],
-                            _p(s["vmin"]), _p(s["vmax"]), _p(s["log"]), _p(s["bright"]),
-                            _p(s["absorb"]), _p(s["mode"]), _p(ca), cam.projection,
-                            cam.width, cam.height, scene.sigma_over_h, scene.trunc_f,
-                            pal.shape[0], _p(pal), pi.shape[0], _p(pi), _p(pj), _p(iin), _p(out))
+    lib().orc_render_pixels(*m.args(), _p(m.cam), cam.projection, cam.width, cam.height,
+                            pi.shape[0], _p(pi), _p(pj), _p(iin), _p(out))
     return out
 
 
 def raymarch(x, y, z, h, rho0, E, A, cam, sigma_over_h=1.0, trunc_f=2.0, steps_per_sigma=120,
-             img_in=None) -> np.ndarray:
+             img_in=None, kernel=0) -> np.ndarray:
     """Brute-force RK4 integration of Eq. (1) through the summed density,
     orthographic cameras only.  E, A: (n, 3) per-particle emission and
-    absorption.  Returns planar [3][H][W] FP64."""
+    absorption.  kernel 0: density kept on rays within f sigma of the
+    centre; kernel 1: density cut to the sphere of radius f sigma.
+    Returns planar [3][H][W] FP64."""
     x, y, z, h = (_f32(a) for a in (x, y, z, h))
     rho0 = np.ascontiguousarray(rho0, np.float64)
     E = np.ascontiguousarray(E, np.float64)
@@ -204,7 +243,8 @@ def raymarch(x, y, z, h, rho0, E, A, cam, sigma_over_h=1.0, trunc_f=2.0, steps_p
     iin = None if img_in is None else np.ascontiguousarray(img_in, np.float64)
     ca = cam_array(cam)
     lib().orc_raymarch(x.shape[0], _p(x), _p(y), _p(z), _p(h), _p(rho0), _p(E), _p(A), _p(ca),
-                       W, H, sigma_over_h, trunc_f, steps_per_sigma, _p(iin), _p(out))
+                       W, H, sigma_over_h, trunc_f, int(kernel), steps_per_sigma, _p(iin),
+                       _p(out))
     return out
 
 

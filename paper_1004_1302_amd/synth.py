@@ -27,6 +27,10 @@ ORTHO = 0
 PERSPECTIVE = 1
 ADDITIVE = 0
 ORDERED = 1
+COLOUR_PALETTE = 0   # a scalar through the colour look-up table
+COLOUR_VECTOR = 1    # three vector components map to r, g, b
+KERNEL_GAUSS2D = 0   # Gaussian column cut at impact parameter f sigma
+KERNEL_TRUNC3D = 1   # Gaussian density cut to the sphere r <= f sigma
 
 
 # --------------------------------------------------------------------------
@@ -128,6 +132,7 @@ class Species:
     brightness: float = 1.0
     absorption: float = 0.0
     mode: int = ADDITIVE
+    colour: int = COLOUR_PALETTE
 
 
 @dataclass
@@ -147,6 +152,11 @@ class Scene:
     sigma_over_h: float = 1.0
     trunc_f: float = 2.0
     name: str = ""
+    value_g: np.ndarray | None = None   # 2nd and 3rd vector components
+    value_b: np.ndarray | None = None   # (vector-coloured species)
+    palette_absorb: np.ndarray | None = None  # absorption palette; None = palette
+    kernel: int = KERNEL_GAUSS2D
+    emission_is_source: int = 0
 
     @property
     def n(self) -> int:
@@ -157,7 +167,9 @@ class Scene:
             return None if a is None else np.ascontiguousarray(a[idx])
         return Scene(s(self.x), s(self.y), s(self.z), s(self.h), s(self.value),
                      self.camera, self.species_params, s(self.species), s(self.rho0),
-                     self.palette, self.sigma_over_h, self.trunc_f, self.name)
+                     self.palette, self.sigma_over_h, self.trunc_f, self.name,
+                     s(self.value_g), s(self.value_b), self.palette_absorb, self.kernel,
+                     self.emission_is_source)
 
 
 def _lognormal_mean(rng, mean, sigma, n):

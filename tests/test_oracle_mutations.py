@@ -15,12 +15,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "splotch_oracle.c")
 
 MUTATIONS = {
-    "half_exponent": ("double tau = e->rho0 * exp(-q2);", "double tau = e->rho0 * exp(-0.5 * q2);"),
-    "drop_rho0": ("double tau = e->rho0 * exp(-q2);", "double tau = exp(-q2);"),
-    "drop_phi": ("I[ch] = I[ch] * exp(-xx) + e->E[ch] * tau * phi(xx);",
-                 "I[ch] = I[ch] * exp(-xx) + e->E[ch] * tau;"),
-    "front_to_back_painter": ("for (int64_t a = m - 1; a >= 0; --a) {",
-                              "for (int64_t a = 0; a < m; ++a) {"),
+    "half_exponent": ("double g = exp(-q2);", "double g = exp(-0.5 * q2);"),
+    "drop_rho0": ("double tau = e->rho0 * column(st, q2);", "double tau = column(st, q2);"),
+    "drop_phi": ("*I = *I * ex + E * tau * phi(xx);", "*I = *I * ex + E * tau;"),
+    "front_to_back_painter": ("for (int64_t a = nlist - 1; a >= 0; --a) {",
+                              "for (int64_t a = 0; a < nlist; ++a) {"),
     "swap_screen_axes": ("double u = xc * s + 0.5 * (double)c->W;\n    double v = yc * s + 0.5 * (double)c->H;",
                          "double u = yc * s + 0.5 * (double)c->W;\n    double v = xc * s + 0.5 * (double)c->H;"),
     "flip_x": ("double u = xc * s + 0.5 * (double)c->W;", "double u = -xc * s + 0.5 * (double)c->W;"),
@@ -29,11 +28,28 @@ MUTATIONS = {
     "pixel_corner_not_centre": ("double dx = ((double)i + 0.5) - e->p.u;", "double dx = ((double)i) - e->p.u;"),
     "bbox_off_by_half": ("double a = (u - r) - 0.5, b = (u + r) - 0.5;", "double a = (u - r), b = (u + r);"),
     "palette_no_interp": ("double w = p - (double)k;", "double w = 0.0;"),
-    "absorb_uses_emission": ("e.A[ch] = sp->mode[s] == 1 ? (double)sp->absorb[s] * col[ch] : 0.0;",
-                             "e.A[ch] = sp->mode[s] == 1 ? (double)sp->bright[s] * col[ch] : 0.0;"),
+    "absorb_uses_emission": ("A[c] = st->mode[s] == 1 ? (double)st->absorb[s] * ca[c] : 0.0;",
+                             "A[c] = st->mode[s] == 1 ? (double)st->bright[s] * ca[c] : 0.0;"),
     "no_log_scale": ("gv = log10((double)value);\n        g0 = log10((double)vmin);\n        g1 = log10((double)vmax);",
                      "gv = value;\n        g0 = vmin;\n        g1 = vmax;"),
     "depth_cull_inclusive_near": ("if (!(zc > c->znear && zc <= c->zfar)) {", "if (!(zc > c->znear - 1e9 && zc <= c->zfar)) {"),
+    # 3-D truncation of the density
+    "trunc3d_no_erf": ("g *= erf(sqrt(rem > 0.0 ? rem : 0.0));", "g *= 1.0;"),
+    "trunc3d_erf_of_f": ("g *= erf(sqrt(rem > 0.0 ? rem : 0.0));", "g *= erf(f);"),
+    # emission read as a source function
+    "source_reading_ignored": ("if (st->emission_is_source && st->mode[s] == 1) E[c] = A[c] * E[c];", ""),
+    "source_reading_on_additive": ("if (st->emission_is_source && st->mode[s] == 1) E[c] = A[c] * E[c];",
+                                   "if (st->emission_is_source) E[c] = A[c] * E[c];"),
+    # general colouring
+    "absorb_palette_ignored": ("if (st->pal_abs)\n", "if (0)\n"),
+    "vector_swap_g_b": ("const float comp[3] = {P->value[k], P->value_g[k], P->value_b[k]};",
+                        "const float comp[3] = {P->value[k], P->value_b[k], P->value_g[k]};"),
+    "vector_range_first_component": ("            nc = 3;\n", "            nc = 1;\n"),
+    # compensated summation
+    "compensation_dropped": ("img[ch * np + (size_t)j * W + i] += cmp[ch * pc + (size_t)(j - ra) * W + i];",
+                             "img[ch * np + (size_t)j * W + i] += 0.0 * cmp[ch * pc + (size_t)(j - ra) * W + i];"),
+    "row_bands_reordered": ("paint_rows(st, v, list + cnt[b], cnt[b + 1] - cnt[b], W, H, ra, rb, img_out);",
+                            "paint_rows(st, v, list + cnt[b], cnt[b + 1] - cnt[b] - (cnt[b + 1] > cnt[b]), W, H, ra, rb, img_out);"),
 }
 
 

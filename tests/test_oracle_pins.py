@@ -141,7 +141,7 @@ def test_superposition_additive(orc):
 
 # ---------------------------------------------------------------- P6 / P9
 def _ray_vs_splat(orc, n, seed, mode, depth_disjoint=False, e_eq_a=False, img_in=None,
-                  f=2.0, size=24):
+                  f=2.0, size=24, kernel=0):
     """Render with the oracle and integrate Eq. (1) by brute force; E and A
     for the marcher are taken from the palette by hand."""
     cam = synth.ortho_unit_square(size, size)
@@ -161,6 +161,7 @@ def _ray_vs_splat(orc, n, seed, mode, depth_disjoint=False, e_eq_a=False, img_in
     bright, absorb = float(np.float32(0.9)), float(np.float32(0.9 if e_eq_a else 1.6))
     sp = [synth.Species(vmin=0.0, vmax=2.0, brightness=bright, absorption=absorb, mode=mode)]
     sc = one(x, y, z, h, v, cam=cam, rho0=r0, f=f, pal=pal, sp=sp)
+    sc.kernel = kernel
     splat = orc.render(sc, img_in=img_in)
     E = np.zeros((n, 3))
     A = np.zeros((n, 3))
@@ -169,7 +170,7 @@ def _ray_vs_splat(orc, n, seed, mode, depth_disjoint=False, e_eq_a=False, img_in
         E[k] = bright * col
         A[k] = absorb * col if mode == synth.ORDERED else 0.0
     ray = orc.raymarch(sc.x, sc.y, sc.z, sc.h, sc.rho0.astype(np.float64), E, A, cam,
-                       trunc_f=f, img_in=img_in)
+                       trunc_f=f, img_in=img_in, kernel=kernel)
     return splat, ray
 
 
@@ -419,3 +420,147 @@ def test_render_pixels_matches_full_render(orc):
     pj = rng.integers(0, 90, 300)
     got = orc.render_pixels(sc, pi, pj)
     assert np.allclose(got, full[:, pj, pi].T, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------- 3-D truncation
+def _f3d(f):
+    """Fraction of a Gaussian ball's mass inside radius f sigma:
+    erf(f) - (2 f / sqrt(pi)) exp(-f^2) (radial integral of r^2 e^{-r^2})."""
+    return math.erf(f) - 2.0 * f / math.sqrt(math.pi) * math.exp(-f * f)
+
+
+@pytest.mark.parametrize("f", [2.0, 1.5])
+def test_trunc3d_flux_is_ball_mass(orc, f):
+    """Density cut to the sphere r <= f sigma (Section 2, first assumption
+    read in 3-D): the image integrates the particle's mass, rho0 pi sigma^2
+    times the mass fraction of the truncated ball (0.95399 at f = 2)."""
+    cam = synth.ortho_unit_square(256, 256)
+    sc = one(0.5013, 0.4987, 0.5, 20.0 / 256.0, cam=cam, pal=WHITE, f=f, rho0=1.1)
+    sc.kernel = synth.KERNEL_TRUNC3D
+    img = orc.render(sc)
+    s = float(sc.h[0]) * 256.0
+    r0 = float(np.float32(1.1))
+    assert _f3d(2.0) == pytest.approx(0.95399, abs=1e-5)
+    assert img[0].sum() == pytest.approx(r0 * math.pi * s * s * _f3d(f), rel=1e-3)
+    # the 2-D cut of the same particle holds more: pi sigma^2 (1 - e^{-f^2})
+    sc.kernel = synth.KERNEL_GAUSS2D
+    assert orc.render(sc)[0].sum() > img[0].sum() * 1.01
+
+
+@pytest.mark.parametrize("case", ["additive", "e_eq_a", "disjoint"])
+def test_trunc3d_against_raymarch(orc, case):
+    """The 3-D-truncated column equals a brute-force march through the
+    sphere-cut densities: exactly for additive and E = A renders with
+    overlap, and for particles separated in depth with E != A."""
+    kw = dict(additive=dict(mode=synth.ADDITIVE),
+              e_eq_a=dict(mode=synth.ORDERED, e_eq_a=True, img_in=np.full((3, 24, 24), 0.2)),
+              disjoint=dict(mode=synth.ORDERED, depth_disjoint=True,
+                            img_in=np.full((3, 24, 24), 0.3)))[case]
+    splat, ray = _ray_vs_splat(orc, 6 if case == "disjoint" else 8, 21, kernel=1, **kw)
+    assert np.abs(ray).max() > 0.05
+    assert np.allclose(splat, ray, rtol=0, atol=1e-7 * max(1.0, np.abs(ray).max()))
+
+
+# ---------------------------------------------------------------- emission readings
+def test_emission_is_source_single_particle(orc):
+    """With the emission read as a source function S (Eq. (1) with E = A S),
+    one particle over a constant background gives (I_in - S) e^{-A tau} + S;
+    the additive species is unaffected by that reading."""
+    cam = synth.ortho_unit_square(16, 16)
+    S, Aab = float(np.float32(0.7)), float(np.float32(1.9))
+    sp = [synth.Species(vmin=0.0, vmax=2.0, brightness=S, absorption=Aab, mode=synth.ORDERED)]
+    sc = one(0.5, 0.5, 0.5, 3.0 / 16.0, 2.0, cam=cam, pal=WHITE, sp=sp, rho0=0.8)
+    sc.emission_is_source = 1
+    iin = np.full((3, 16, 16), 0.25)
+    img = orc.render(sc, img_in=iin)
+    r0 = float(np.float32(0.8))
+    tau = r0 * math.exp(-(0.5 ** 2 + 0.5 ** 2) / 9.0)
+    assert img[1, 8, 8] == pytest.approx((0.25 - S) * math.exp(-Aab * tau) + S, rel=1e-12)
+    ray = orc.raymarch(sc.x, sc.y, sc.z, sc.h, np.array([r0]), np.full((1, 3), Aab * S),
+                       np.full((1, 3), Aab), cam, img_in=iin)
+    assert np.allclose(img, ray, atol=1e-9)
+    add = [synth.Species(vmin=0.0, vmax=2.0, brightness=S, absorption=Aab, mode=synth.ADDITIVE)]
+    sa = one(0.5, 0.5, 0.5, 3.0 / 16.0, 2.0, cam=cam, pal=WHITE, sp=add, rho0=0.8)
+    base = orc.render(sa)
+    sa.emission_is_source = 1
+    assert np.array_equal(orc.render(sa), base)
+
+
+def test_absorption_palette(orc):
+    """A separate absorption look-up table: a particle that absorbs only in
+    red (absorption palette red) but emits white attenuates the red channel
+    of the light behind it and adds E tau to green and blue (Eq. (1) per
+    channel, r, g, b independent)."""
+    cam = synth.ortho_unit_square(16, 16)
+    E, Aab = float(np.float32(0.6)), float(np.float32(2.5))
+    sp = [synth.Species(vmin=0.0, vmax=2.0, brightness=E, absorption=Aab, mode=synth.ORDERED)]
+    sc = one(0.5, 0.5, 0.5, 3.0 / 16.0, 2.0, cam=cam, pal=WHITE, sp=sp, rho0=0.9)
+    sc.palette_absorb = np.array([[1.0, 0.0, 0.0], [1.0, 0.0, 0.0]], np.float32)
+    iin = np.full((3, 16, 16), 0.5)
+    img = orc.render(sc, img_in=iin)
+    r0 = float(np.float32(0.9))
+    tau = r0 * math.exp(-(0.5 ** 2 + 0.5 ** 2) / 9.0)
+    assert img[0, 8, 8] == pytest.approx((0.5 - E / Aab) * math.exp(-Aab * tau) + E / Aab,
+                                         rel=1e-12)
+    assert img[1, 8, 8] == pytest.approx(0.5 + E * tau, rel=1e-12)
+    assert img[2, 8, 8] == pytest.approx(0.5 + E * tau, rel=1e-12)
+    ray = orc.raymarch(sc.x, sc.y, sc.z, sc.h, np.array([r0]), np.full((1, 3), E),
+                       np.array([[Aab, 0.0, 0.0]]), cam, img_in=iin)
+    assert np.allclose(img, ray, atol=1e-9)
+
+
+def test_vector_colour(orc):
+    """Three vector components map to r, g, b directly (Section 2, last
+    paragraph), each normalised with the species' range; the automatic
+    range spans all three components."""
+    cam = synth.ortho_unit_square(32, 32)
+    sp = [synth.Species(vmin=0.0, vmax=2.0, brightness=1.5, colour=synth.COLOUR_VECTOR)]
+    sc = one(16.5 / 32, 16.5 / 32, 0.5, 2.0 / 32, 0.5, cam=cam, sp=sp, rho0=0.5)
+    sc.value_g = np.array([1.0], np.float32)
+    sc.value_b = np.array([1.5], np.float32)
+    img = orc.render(sc)
+    b = float(np.float32(1.5)) * 0.5
+    assert list(img[:, 16, 16]) == pytest.approx([b * 0.25, b * 0.5, b * 0.75], rel=1e-12)
+    rng = np.random.default_rng(4)
+    n = 300
+    sc2 = one(rng.uniform(0, 1, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n),
+              np.full(n, 0.01), rng.uniform(1, 2, n), cam=cam,
+              sp=[synth.Species(colour=synth.COLOUR_VECTOR), synth.Species()],
+              species=rng.integers(0, 2, n))
+    sc2.value_g = rng.uniform(-3, 0, n).astype(np.float32)
+    sc2.value_b = rng.uniform(2, 5, n).astype(np.float32)
+    lo, hi = orc.value_range(sc2)
+    v = sc2.species == 0
+    assert lo[0] == sc2.value_g[v].min() and hi[0] == sc2.value_b[v].max()
+    assert lo[1] == sc2.value[~v].min() and hi[1] == sc2.value[~v].max()
+
+
+# ---------------------------------------------------------------- compensated sum
+def test_additive_sum_is_compensated(orc):
+    """n identical emission-only particles on one pixel sum to n times one
+    particle's contribution within 2 ulp (compensated FP64 summation of the
+    A = 0 case of Eq. (1)); a plain running sum drifts by many ulp."""
+    n = 200_000
+    cam = synth.ortho_unit_square(8, 8)
+    one_p = one(4.3 / 8, 4.6 / 8, 0.5, 1.1 / 8, 1.3, cam=cam, pal=synth.palette(256))
+    y = orc.render(one_p)[:, 4, 4]
+    many = one(np.full(n, 4.3 / 8), np.full(n, 4.6 / 8), np.full(n, 0.5), np.full(n, 1.1 / 8),
+               np.full(n, 1.3), cam=cam, pal=synth.palette(256))
+    got = orc.render(many)[:, 4, 4]
+    for c in range(3):
+        exact = math.fsum([float(y[c])] * n)
+        assert abs(got[c] - exact) <= 2 * np.spacing(exact)
+    naive = 0.0
+    for _ in range(n):
+        naive += float(y[0])
+    assert abs(naive - math.fsum([float(y[0])] * n)) > 8 * np.spacing(naive)
+
+
+def test_row_band_render_is_identical(orc):
+    """The row-band parallel render paints every pixel with the same
+    back-to-front sequence as the single-thread one: identical bits."""
+    sc = synth.nfw_halos(20000, seed=7, n_halos=15, grid=32, width=100, height=70)
+    iin = np.random.default_rng(3).uniform(0, 0.2, (3, 70, 100))
+    a = orc.render(sc, img_in=iin)
+    for band in (1, 7, 16):
+        assert np.array_equal(orc.render_rows(sc, img_in=iin, band=band), a)
