@@ -51,16 +51,32 @@ typedef enum {
 
 enum { SPLOTCH_ORTHO = 0, SPLOTCH_PERSPECTIVE = 1 };
 enum { SPLOTCH_ADDITIVE = 0, SPLOTCH_ORDERED = 1 };
+/* How a species' particles get their colour (Section 2, last paragraph). */
+enum { SPLOTCH_COLOUR_PALETTE = 0, SPLOTCH_COLOUR_VECTOR = 1 };
+/* Which column of the particle's density a pixel ray sees (Section 2,
+ * first assumption: the density is set to zero beyond f sigma).
+ * GAUSS2D: the cut is on the ray's impact parameter d, tau = rho0 exp(-q^2)
+ *          with q = d / sigma_s, for d <= f sigma_s.
+ * TRUNC3D: the density is cut to the ball r <= f sigma, so the column is
+ *          tau = rho0 exp(-q^2) erf(sqrt(f^2 - q^2)).
+ * Both are normalised so that the untruncated column at d = 0 is rho0. */
+enum { SPLOTCH_KERNEL_GAUSS2D = 0, SPLOTCH_KERNEL_TRUNC3D = 1 };
 
 #define SPLOTCH_MAX_SPECIES 8
 #define SPLOTCH_MAX_DIM 16384 /* maximum image width and height in pixels */
 
 /* Particle set, structure of arrays, all device pointers of n elements.
  * x, y, z: world position; h: smoothing length (sigma = sigma_over_h * h);
- * value: the scalar mapped to colour (Section 2, colour look-up table);
+ * value: the scalar mapped to colour (Section 2, colour look-up table), or
+ *        the first component of a vector quantity for species coloured by
+ *        a vector;
  * rho0: optional density amplitude / optical-depth scale per particle
  *       (Section 2, optical depth modulated by another scalar), NULL = 1;
- * species: optional species tag per particle, NULL = species 0.
+ * species: optional species tag per particle, NULL = species 0;
+ * value_g, value_b: second and third vector components (Section 2, last
+ *       paragraph: a vector's components mapped directly to r, g, b).
+ *       Required when any species uses SPLOTCH_COLOUR_VECTOR, else unread
+ *       (may be NULL).
  * n may be 0; n must be below 2^32. */
 typedef struct splotch_particles {
     int64_t n;
@@ -69,6 +85,7 @@ typedef struct splotch_particles {
     const float *value;
     const float *rho0;
     const uint8_t *species;
+    const float *value_g, *value_b;
 } splotch_particles;
 
 /* Camera (host struct).  right, up, fwd: orthonormal FP32 frame with
@@ -90,12 +107,18 @@ typedef struct splotch_camera {
     float z_near, z_far;
 } splotch_camera;
 
-/* Colour look-up table (Section 2): n_entries >= 2 RGB triples, device,
+/* Colour look-up tables (Section 2): n_entries >= 2 RGB triples, device,
  * interleaved r,g,b, float32.  A normalised scalar t in [0,1] is mapped by
- * linear interpolation at t*(n_entries-1). */
+ * linear interpolation at t*(n_entries-1).  rgb gives the emission colour;
+ * rgb_absorb (n_entries_absorb >= 2 triples) gives the absorption colour of
+ * ORDERED species, so that E and A may differ per channel (Section 2: the
+ * paper's E = A restriction lifted).  rgb_absorb = NULL uses rgb for both
+ * (n_entries_absorb is then ignored). */
 typedef struct splotch_colourmap {
     int32_t n_entries;
     const float *rgb;
+    int32_t n_entries_absorb;
+    const float *rgb_absorb;
 } splotch_colourmap;
 
 /* Per-species colour and transfer settings.
@@ -103,15 +126,22 @@ typedef struct splotch_colourmap {
  * g = log10 when log_scale (values <= 0 give t = 0) or the identity;
  * vmin >= vmax asks the library for the exact min/max of the species'
  * valid particles (positive ones only under log_scale).
- * E_p = brightness * colour(t), A_p = absorption * colour(t) for ORDERED
- * species and A_p = 0 for ADDITIVE species (Eq. (1)).  Absorption equal to
- * brightness is the paper's recommended E = A setting. */
+ * E_p = brightness * colour(t), A_p = absorption * colour_A(t) for ORDERED
+ * species and A_p = 0 for ADDITIVE species (Eq. (1)); colour_A is the
+ * absorption table when the colour map has one, else the emission table.
+ * Absorption equal to brightness with one table is the paper's recommended
+ * E = A setting.
+ * colour = SPLOTCH_COLOUR_VECTOR maps the three components (value, value_g,
+ * value_b) to r, g, b directly: channel c uses t_c, the normalised c-th
+ * component (same range and scale for all three; an automatic range spans
+ * all three components), for both E and A. */
 typedef struct splotch_species {
     float vmin, vmax;
     int32_t log_scale;
     float brightness;
     float absorption;
-    int32_t mode; /* SPLOTCH_ADDITIVE or SPLOTCH_ORDERED */
+    int32_t mode;   /* SPLOTCH_ADDITIVE or SPLOTCH_ORDERED */
+    int32_t colour; /* SPLOTCH_COLOUR_PALETTE (0) or SPLOTCH_COLOUR_VECTOR */
 } splotch_species;
 
 /* Optional statistics (host struct), filled after the render. */
@@ -180,6 +210,14 @@ typedef struct splotch_params {
     void *workspace;     /* device, >= splotch_workspace_size() bytes, 256-aligned */
     size_t workspace_bytes;
     splotch_stats *stats; /* host, may be NULL */
+    int32_t kernel;      /* SPLOTCH_KERNEL_GAUSS2D (0) or SPLOTCH_KERNEL_TRUNC3D */
+    int32_t emission_is_source; /* 0: Eq. (1) as written, each particle adds
+                            I <- I exp(-A tau) + E tau phi(A tau),
+                            phi(x) = (1 - exp(-x))/x.  1: for ORDERED species
+                            E is read as the source function S = E/A, i.e.
+                            Eq. (1) runs with E := A * E, and the update is
+                            I <- (I - E) exp(-A tau) + E.  ADDITIVE species
+                            are unaffected. */
 } splotch_params;
 
 /* Output image: planar float32 [3][height][width], device. */

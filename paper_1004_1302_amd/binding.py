@@ -9,6 +9,8 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+
+import numpy as np
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -17,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libsplotch.so")
 MAX_SPECIES = 8
 ORTHO, PERSPECTIVE = 0, 1
 ADDITIVE, ORDERED = 0, 1
+COLOUR_PALETTE, COLOUR_VECTOR = 0, 1
+KERNEL_GAUSS2D, KERNEL_TRUNC3D = 0, 1
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device", 4: "unsupported",
           5: "capacity"}
@@ -31,7 +35,7 @@ class SplotchError(RuntimeError):
 class Particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("h", C.c_void_p), ("value", C.c_void_p), ("rho0", C.c_void_p),
-                ("species", C.c_void_p)]
+                ("species", C.c_void_p), ("value_g", C.c_void_p), ("value_b", C.c_void_p)]
 
 
 class CameraS(C.Structure):
@@ -42,12 +46,14 @@ class CameraS(C.Structure):
 
 
 class Colourmap(C.Structure):
-    _fields_ = [("n_entries", C.c_int32), ("rgb", C.c_void_p)]
+    _fields_ = [("n_entries", C.c_int32), ("rgb", C.c_void_p), ("n_entries_absorb", C.c_int32),
+                ("rgb_absorb", C.c_void_p)]
 
 
 class SpeciesS(C.Structure):
     _fields_ = [("vmin", C.c_float), ("vmax", C.c_float), ("log_scale", C.c_int32),
-                ("brightness", C.c_float), ("absorption", C.c_float), ("mode", C.c_int32)]
+                ("brightness", C.c_float), ("absorption", C.c_float), ("mode", C.c_int32),
+                ("colour", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -78,7 +84,8 @@ class Params(C.Structure):
                 ("splat_variant", C.c_int32), ("batch_streams", C.c_int32),
                 ("tile_mask", C.c_void_p),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats))]
+                ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats)),
+                ("kernel", C.c_int32), ("emission_is_source", C.c_int32)]
 
 
 class Image(C.Structure):
@@ -177,14 +184,15 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
                   tile=0, profile=False, seg_records=0, tile_mask=None,
-                  splat_variant=0, batch_streams=0) -> Params:
+                  splat_variant=0, batch_streams=0, kernel=0, emission_is_source=0) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
     p.n_species = len(species)
     for k, s in enumerate(species):
         p.species[k] = SpeciesS(float(s.vmin), float(s.vmax), int(s.log_scale),
-                                float(s.brightness), float(s.absorption), int(s.mode))
+                                float(s.brightness), float(s.absorption), int(s.mode),
+                                int(getattr(s, "colour", COLOUR_PALETTE)))
     p.sigma_over_h = float(sigma_over_h)
     p.trunc_f = float(trunc_f)
     p.accumulate = 1 if accumulate else 0
@@ -195,6 +203,8 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.tile_mask = None if tile_mask is None else C.c_void_p(tile_mask.data_ptr())
     p.splat_variant = int(splat_variant)
     p.batch_streams = int(batch_streams)
+    p.kernel = int(kernel)
+    p.emission_is_source = int(emission_is_source)
     return p
 
 
@@ -202,13 +212,29 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _table(t, what):
+    import torch
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != 3:
+        raise ValueError(f"{what} must be contiguous float32 [K, 3]")
+    return int(t.shape[0]), C.c_void_p(t.data_ptr())
+
+
+def colourmap_struct(palette, palette_absorb=None) -> Colourmap:
+    """Emission table and optional absorption table (device [K, 3] float32)."""
+    k, p = _table(palette, "palette")
+    cm = Colourmap(k, p, 0, None)
+    if palette_absorb is not None:
+        cm.n_entries_absorb, cm.rgb_absorb = _table(palette_absorb, "palette_absorb")
+    return cm
+
+
 def particles_struct(parts: dict) -> Particles:
     """parts: dict of contiguous device tensors x, y, z, h, value (float32)
-    and optional rho0 (float32), species (uint8)."""
+    and optional rho0, value_g, value_b (float32), species (uint8)."""
     import torch
     P = Particles()
     n = int(parts["x"].numel())
-    for k in ("x", "y", "z", "h", "value", "rho0"):
+    for k in ("x", "y", "z", "h", "value", "rho0", "value_g", "value_b"):
         t = parts.get(k)
         if t is not None:
             if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
@@ -220,6 +246,8 @@ def particles_struct(parts: dict) -> Particles:
     P.x, P.y, P.z, P.h, P.value = (_ptr(parts[k]) for k in ("x", "y", "z", "h", "value"))
     P.rho0 = _ptr(parts.get("rho0"))
     P.species = _ptr(sp)
+    P.value_g = _ptr(parts.get("value_g"))
+    P.value_b = _ptr(parts.get("value_b"))
     return P
 
 
@@ -285,7 +313,8 @@ def _setup(parts, cam, species, max_pairs, workspace, **kw):
 
 def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, trunc_f=2.0,
            accumulate=False, compensated=False, tile=0, max_pairs=0, workspace=None,
-           stats=False, profile=False, seg_records=0, tile_mask=None, splat_variant=0):
+           stats=False, profile=False, seg_records=0, tile_mask=None, splat_variant=0,
+           palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0):
     """Render into image (planar float32 [3, H, W] device tensor; allocated
     if None).  Returns the image, or (image, stats dict) with stats=True
     (profile=True adds per-stage milliseconds to the stats)."""
@@ -293,17 +322,15 @@ def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, 
     P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
                              trunc_f=trunc_f, accumulate=accumulate, compensated=compensated,
                              tile=tile, profile=profile, seg_records=seg_records,
-                             tile_mask=tile_mask, splat_variant=splat_variant)
+                             tile_mask=tile_mask, splat_variant=splat_variant, kernel=kernel,
+                             emission_is_source=emission_is_source)
     stats = stats or profile
     if image is None:
         image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)
     if image.dtype != torch.float32 or not image.is_contiguous() or \
             tuple(image.shape) != (3, cs.height, cs.width):
         raise ValueError("image must be contiguous float32 [3, H, W]")
-    if palette.dtype != torch.float32 or not palette.is_contiguous() or palette.dim() != 2 \
-            or palette.shape[1] != 3:
-        raise ValueError("palette must be contiguous float32 [K, 3]")
-    cm = Colourmap(int(palette.shape[0]), C.c_void_p(palette.data_ptr()))
+    cm = colourmap_struct(palette, palette_absorb)
     img = Image(C.c_void_p(image.data_ptr()), cs.width, cs.height)
     st = Stats()
     if stats:
@@ -370,7 +397,7 @@ def _side_stream(device):
 def render_batch(parts: dict, cams, palette, species, images=None, *, graph=False,
                  sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False, tile=0,
                  max_pairs=0, seg_records=0, workspace=None, stats=False, splat_variant=0,
-                 streams=1):
+                 streams=1, palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0):
     """Render several camera views of one particle set (splotch_render_batch).
     images: list of [3, H_v, W_v] float32 device tensors (allocated if None).
     graph=True captures the batch into a HIP graph on first use and replays
@@ -388,7 +415,8 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
     prm = params_struct(species, sigma_over_h=sigma_over_h, trunc_f=trunc_f,
                         accumulate=accumulate, compensated=compensated, tile=tile,
                         seg_records=seg_records, splat_variant=splat_variant,
-                        batch_streams=streams)
+                        batch_streams=streams, kernel=kernel,
+                        emission_is_source=emission_is_source)
     T = tile or 16
     big = max(range(nv), key=lambda v: (-(-cs[v].width // T)) * (-(-cs[v].height // T)))
     if workspace is None:
@@ -408,7 +436,7 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
             raise ValueError("each image must be contiguous float32 [3, H, W] of its camera")
     ims = (Image * nv)(*[Image(C.c_void_p(im.data_ptr()), c.width, c.height)
                          for im, c in zip(images, cs)])
-    cm = Colourmap(int(palette.shape[0]), C.c_void_p(palette.data_ptr()))
+    cm = colourmap_struct(palette, palette_absorb)
     st = (Stats * nv)()
     if stats:
         prm.stats = C.cast(st, C.POINTER(Stats))
@@ -439,6 +467,7 @@ class SpeciesParams:
     brightness: float = 1.0
     absorption: float = 0.0
     mode: int = ADDITIVE
+    colour: int = COLOUR_PALETTE
 
 
 def scene_to_device(scene, device="cuda"):
@@ -454,5 +483,22 @@ def scene_to_device(scene, device="cuda"):
         parts["rho0"] = t(scene.rho0, torch.float32)
     if scene.species is not None:
         parts["species"] = t(scene.species, torch.uint8)
+    for k in ("value_g", "value_b"):
+        a = getattr(scene, k, None)
+        if a is not None:
+            parts[k] = t(a, torch.float32)
     pal = torch.from_numpy(scene.palette).to(device=device, dtype=torch.float32).contiguous()
     return parts, pal
+
+
+def scene_options(scene, device="cuda") -> dict:
+    """Render keyword arguments a host synth.Scene carries besides its
+    particles, palette and species: footprint scale and cut, column kernel,
+    emission reading and the absorption table (copied to the device)."""
+    import torch
+    pa = getattr(scene, "palette_absorb", None)
+    return dict(sigma_over_h=float(scene.sigma_over_h), trunc_f=float(scene.trunc_f),
+                kernel=int(getattr(scene, "kernel", KERNEL_GAUSS2D)),
+                emission_is_source=int(getattr(scene, "emission_is_source", 0)),
+                palette_absorb=None if pa is None else
+                torch.from_numpy(np.ascontiguousarray(pa, np.float32)).to(device))

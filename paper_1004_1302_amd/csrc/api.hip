@@ -169,7 +169,12 @@ splotch_status validate_params(const splotch_params *p) {
             return SPLOTCH_E_INVALID_ARG;
         if (isnan(q.vmin) || isnan(q.vmax)) return SPLOTCH_E_INVALID_ARG;
         if (q.log_scale && q.vmin < q.vmax && !(q.vmin > 0.0f)) return SPLOTCH_E_INVALID_ARG;
+        if (q.colour != SPLOTCH_COLOUR_PALETTE && q.colour != SPLOTCH_COLOUR_VECTOR)
+            return SPLOTCH_E_INVALID_ARG;
     }
+    if (p->kernel != SPLOTCH_KERNEL_GAUSS2D && p->kernel != SPLOTCH_KERNEL_TRUNC3D)
+        return SPLOTCH_E_INVALID_ARG;
+    if (p->emission_is_source != 0 && p->emission_is_source != 1) return SPLOTCH_E_INVALID_ARG;
     return SPLOTCH_OK;
 }
 
@@ -214,8 +219,31 @@ SpeciesDev species_dev(const splotch_params *p) {
         s.log_scale[k] = q.log_scale ? 1 : 0;
         s.ordered[k] = q.mode == SPLOTCH_ORDERED;
         s.auto_range[k] = !(q.vmin < q.vmax);
+        s.vector[k] = q.colour == SPLOTCH_COLOUR_VECTOR;
+        s.any_vector |= s.vector[k];
     }
     return s;
+}
+
+splotch_status validate_colourmap(const splotch_colourmap *m) {
+    if (!m || m->n_entries < 2 || !m->rgb) return SPLOTCH_E_INVALID_ARG;
+    if (m->rgb_absorb && m->n_entries_absorb < 2) return SPLOTCH_E_INVALID_ARG;
+    return SPLOTCH_OK;
+}
+
+// Colour and column settings of the splat (shared by single and batched
+// renders).
+void splat_colour_args(SplatArgs *sa, const splotch_particles *P, const splotch_colourmap *m,
+                       const splotch_params *p) {
+    sa->palette = m->rgb;
+    sa->n_pal = m->n_entries;
+    sa->pal_abs = m->rgb_absorb;
+    sa->n_pal_abs = m->rgb_absorb ? m->n_entries_absorb : 0;
+    sa->value_g = P->value_g;
+    sa->value_b = P->value_b;
+    sa->kernel3d = p->kernel == SPLOTCH_KERNEL_TRUNC3D ? 1 : 0;
+    sa->source = p->emission_is_source ? 1 : 0;
+    sa->sp = species_dev(p);
 }
 
 #define TRY(expr)                                      \
@@ -298,6 +326,8 @@ splotch_status run_project(const Ctx &c, const splotch_particles *P, const splot
     a.value = P->value;
     a.rho0 = P->rho0;
     a.species = P->species;
+    a.value_g = P->value_g;
+    a.value_b = P->value_b;
     a.n = P->n;
     a.soh = (double)p->sigma_over_h;
     a.f = (double)p->trunc_f;
@@ -512,6 +542,10 @@ splotch_status prepare(const splotch_particles *P, const splotch_camera *cam,
     if ((st = validate_particles(P)) != SPLOTCH_OK) return st;
     if ((st = validate_camera(cam)) != SPLOTCH_OK) return st;
     if ((st = validate_params(p)) != SPLOTCH_OK) return st;
+    for (int s = 0; s < p->n_species; ++s)
+        if (p->species[s].colour == SPLOTCH_COLOUR_VECTOR && P->n > 0 &&
+            (!P->value_g || !P->value_b))
+            return SPLOTCH_E_INVALID_ARG;
     if (!p->workspace || (reinterpret_cast<uintptr_t>(p->workspace) & 255u) != 0)
         return SPLOTCH_E_WORKSPACE;
     if (!fit_capacity(P->n, cam, p, p->workspace_bytes, &c->L)) return SPLOTCH_E_WORKSPACE;
@@ -653,9 +687,7 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         sa.max_slots = c.L.max_slots;
         sa.max_items = c.L.max_items;
         sa.seg_len = c.at<uint32_t>(c.L.seg_len);
-        sa.palette = cmap->rgb;
-        sa.n_pal = cmap->n_entries;
-        sa.sp = species_dev(p);
+        splat_colour_args(&sa, P, cmap, p);
         sa.image = image->rgb;
         sa.member_count = c.at<unsigned long long>(c.L.mcount);
         sa.tile_mask = p->tile_mask;
@@ -787,7 +819,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     Ctx c;
     splotch_status st = prepare(P, cam, p, &c);
     if (st != SPLOTCH_OK) return st;
-    if (!cmap || cmap->n_entries < 2 || !cmap->rgb) return SPLOTCH_E_INVALID_ARG;
+    if ((st = validate_colourmap(cmap)) != SPLOTCH_OK) return st;
     if (!img || !img->rgb || img->width != cam->width || img->height != cam->height)
         return SPLOTCH_E_INVALID_ARG;
     const int64_t n = P->n;
@@ -805,9 +837,7 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.rec = c.at<Rec>(c.L.rec);
     sa.tile_start = c.at<uint32_t>(c.L.tstart);
     sa.tile_end = c.at<uint32_t>(c.L.tend);
-    sa.palette = cmap->rgb;
-    sa.n_pal = cmap->n_entries;
-    sa.sp = species_dev(p);
+    splat_colour_args(&sa, P, cmap, p);
     sa.image = img->rgb;
     sa.width = cam->width;
     sa.height = cam->height;
@@ -933,7 +963,7 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
             big = v;
         }
     }
-    if (!cmap || cmap->n_entries < 2 || !cmap->rgb) return SPLOTCH_E_INVALID_ARG;
+    if ((st = validate_colourmap(cmap)) != SPLOTCH_OK) return st;
     if (p->batch_streams < 0 || p->batch_streams > kMaxLanes) return SPLOTCH_E_INVALID_ARG;
     const int K = std::max(1, std::min<int>(p->batch_streams, n_views));
     Ctx c;

@@ -28,7 +28,9 @@ struct SpeciesDev {
     float vmin[kMaxSpecies], vmax[kMaxSpecies];
     float brightness[kMaxSpecies], absorption[kMaxSpecies];
     int log_scale[kMaxSpecies], ordered[kMaxSpecies], auto_range[kMaxSpecies];
+    int vector[kMaxSpecies];  // 1: the three vector components are r, g, b
     int n;
+    int any_vector;
 };
 
 // Projected particle record: 32 bytes, two uint4.
@@ -48,6 +50,7 @@ struct ProjectArgs {
     SpeciesDev sp;
     const float *x, *y, *z, *h, *value, *rho0;
     const uint8_t *species;
+    const float *value_g, *value_b;  // vector components 2 and 3 (vector species)
     int64_t n;
     double soh, f;
     int tile, ntx;
@@ -173,6 +176,11 @@ struct SplatArgs {
     const uint32_t *seg_len;    // device: records per segment for this pass
     const float *palette;
     int n_pal;
+    const float *pal_abs;        // absorption table, null = the emission table
+    int n_pal_abs;
+    const float *value_g, *value_b;  // vector components 2 and 3 (vector species)
+    int kernel3d;                // 1: column of the density cut to the f sigma ball
+    int source;                  // 1: emission of ordered species is a source function
     SpeciesDev sp;
     float *image;
     unsigned long long *member_count;  // [2 per tile]: all, absorbing; summed over chunks

@@ -152,14 +152,35 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
         int sp = a.species ? (int)a.species[k] : 0;
         float r0 = a.rho0 ? a.rho0[k] : 1.0f;
         Proj p;
-        const bool valid = particle_valid(x, y, z, h, v, r0, sp, a.sp.n);
-        if (valid && a.sp.auto_range[sp] && (!a.sp.log_scale[sp] || v > 0.0f)) {
-            const uint32_t ob = order_bits(v);
+        bool valid = particle_valid(x, y, z, h, v, r0, sp, a.sp.n);
+        // vector-coloured species: all three components must be finite, and
+        // an automatic range spans all three
+        const bool vec = a.sp.any_vector && valid && a.sp.vector[sp];
+        float vg = 0.0f, vb = 0.0f;
+        if (vec) {
+            vg = a.value_g[k];
+            vb = a.value_b[k];
+            valid = finite_f(vg) && finite_f(vb);
+        }
+        if (valid && a.sp.auto_range[sp]) {
+            const int ls = a.sp.log_scale[sp];
+            uint32_t olo = 0xFFFFFFFFu, ohi = 0u;
+            if (!ls || v > 0.0f) olo = ohi = order_bits(v);
+            if (vec) {
+                if (!ls || vg > 0.0f) {
+                    olo = min(olo, order_bits(vg));
+                    ohi = max(ohi, order_bits(vg));
+                }
+                if (!ls || vb > 0.0f) {
+                    olo = min(olo, order_bits(vb));
+                    ohi = max(ohi, order_bits(vb));
+                }
+            }
 #pragma unroll
             for (int q = 0; q < kMaxSpecies; ++q)
                 if (q == sp) {
-                    lo[q] = min(lo[q], ob);
-                    hi[q] = max(hi[q], ob);
+                    lo[q] = min(lo[q], olo);
+                    hi[q] = max(hi[q], ohi);
                 }
         }
         if (!valid) {

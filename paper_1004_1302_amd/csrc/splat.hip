@@ -157,27 +157,57 @@ struct Expanded {
     float e[3], ab[3];
 };
 
+// Linear interpolation in a K-entry RGB table at t (K - 1), t in [0, 1].
+__device__ __forceinline__ void palette_rgb(const float *pal, int K, float t, float &r, float &g,
+                                            float &b) {
+#pragma clang fp contract(off)
+    const float pp = t * (float)(K - 1);
+    int kk = (int)floorf(pp);
+    kk = kk > K - 2 ? K - 2 : kk;
+    const float w1 = pp - (float)kk, w0 = 1.0f - w1;
+    const float *c0 = pal + 3 * kk;
+    r = c0[0] * w0 + c0[3] * w1;
+    g = c0[1] * w0 + c0[4] * w1;
+    b = c0[2] * w0 + c0[5] * w1;
+}
+
+// Section 2, last paragraph: E = brightness c_E, A = absorption c_A with the
+// colours from the look-up tables at the normalised scalar, or, for
+// vector-coloured species, the three normalised components as r, g, b for
+// both.  Under the source-function reading an ordered species emits A S.
+// idx: the particle's index (vector components are read from the particle
+// arrays; the record keeps only the first).
 __device__ __forceinline__ Expanded expand_loaded(const SplatArgs &a, uint4 ra, uint4 rb,
-                                                  const float *vmin, const float *vmax) {
+                                                  uint32_t idx, const float *vmin,
+                                                  const float *vmax) {
 #pragma clang fp contract(off)
     const int sp = (int)(ra.x >> 28);
-    const float t = normalise_value(__uint_as_float(rb.z), vmin[sp], vmax[sp], a.sp.log_scale[sp]);
+    const int ls = a.sp.log_scale[sp];
     const float rho0 = __uint_as_float(rb.w);
-    const float pp = t * (float)(a.n_pal - 1);
-    int kk = (int)floorf(pp);
-    kk = kk > a.n_pal - 2 ? a.n_pal - 2 : kk;
-    const float w1 = pp - (float)kk, w0 = 1.0f - w1;
-    const float *c0 = a.palette + 3 * kk;
-    const float cr = c0[0] * w0 + c0[3] * w1;
-    const float cg = c0[1] * w0 + c0[4] * w1;
-    const float cb = c0[2] * w0 + c0[5] * w1;
-    const float eb = a.sp.brightness[sp] * rho0;
     const bool ord = a.sp.ordered[sp] != 0;
+    float cr, cg, cb, ar, ag, abb;
+    if (a.sp.any_vector && a.sp.vector[sp]) {
+        cr = normalise_value(__uint_as_float(rb.z), vmin[sp], vmax[sp], ls);
+        cg = normalise_value(a.value_g[idx], vmin[sp], vmax[sp], ls);
+        cb = normalise_value(a.value_b[idx], vmin[sp], vmax[sp], ls);
+        ar = cr;
+        ag = cg;
+        abb = cb;
+    } else {
+        const float t = normalise_value(__uint_as_float(rb.z), vmin[sp], vmax[sp], ls);
+        palette_rgb(a.palette, a.n_pal, t, cr, cg, cb);
+        if (a.pal_abs && ord) {
+            palette_rgb(a.pal_abs, a.n_pal_abs, t, ar, ag, abb);
+        } else {
+            ar = cr;
+            ag = cg;
+            abb = cb;
+        }
+    }
+    const float eb = a.sp.brightness[sp] * rho0;
     const float ab = ord ? a.sp.absorption[sp] * rho0 : 0.0f;
     Expanded x;
     x.b0 = ra.x;
-    x.b1 = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? kEmitOnly : 0u) |
-           ((ab != 0.0f && ab == eb) ? kEmitEqAbsorb : 0u);
     x.ur = __uint_as_float(ra.z);
     x.vr = __uint_as_float(ra.w);
     x.r2 = __uint_as_float(rb.x);
@@ -185,15 +215,40 @@ __device__ __forceinline__ Expanded expand_loaded(const SplatArgs &a, uint4 ra, 
     x.e[0] = eb * cr;
     x.e[1] = eb * cg;
     x.e[2] = eb * cb;
-    x.ab[0] = ab * cr;
-    x.ab[1] = ab * cg;
-    x.ab[2] = ab * cb;
+    x.ab[0] = ab * ar;
+    x.ab[1] = ab * ag;
+    x.ab[2] = ab * abb;
+    if (a.source && ord) {
+        // E := A S per channel: rho0 (A c_A) (E c_E)
+        const float a0 = a.sp.absorption[sp];
+        x.e[0] *= a0 * ar;
+        x.e[1] *= a0 * ag;
+        x.e[2] *= a0 * abb;
+    }
+    const bool same = x.e[0] == x.ab[0] && x.e[1] == x.ab[1] && x.e[2] == x.ab[2];
+    x.b1 = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? kEmitOnly : 0u) |
+           ((ab != 0.0f && same) ? kEmitEqAbsorb : 0u);
     return x;
 }
 
 __device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t idx,
                                                   const float *vmin, const float *vmax) {
-    return expand_loaded(a, a.rec[idx].a, a.rec[idx].b, vmin, vmax);
+    return expand_loaded(a, a.rec[idx].a, a.rec[idx].b, idx, vmin, vmax);
+}
+
+// Column of the density along a member pixel's ray per unit rho0, from the
+// squared distance d2 (pixels^2), the record's r2 = (f sigma_s)^2 and
+// qs = log2(e) / sigma_s^2: exp(-q^2), times erf(sqrt(f^2 - q^2)) when the
+// density is cut to the f sigma ball (f^2 - q^2 = (r2 - d2) / sigma_s^2).
+template <bool K3D>
+__device__ __forceinline__ float column_weight(float d2, float r2, float qs) {
+#pragma clang fp contract(off)
+    float w = __builtin_amdgcn_exp2f(-d2 * qs);
+    if (K3D) {
+        const float rem = fmaxf(r2 - d2, 0.0f) * (qs * 0.6931471805599453f);
+        w *= erff(sqrtf(rem));
+    }
+    return w;
 }
 
 // Records staged per batch: B indices of at most 8 bits per lane list.
@@ -298,7 +353,8 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
                 const uint32_t b0 = s_b0[r], b1 = s_b1[r];
                 const int i0 = (int)(b0 & kBboxMask), j0 = (int)(b1 & kBboxMask);
                 const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
-                const float w = __builtin_amdgcn_exp2f(-d2 * s_qs[r]);  // exp(-q^2)
+                const float w = a.kernel3d ? column_weight<true>(d2, s_r2[r], s_qs[r])
+                                           : column_weight<false>(d2, s_r2[r], s_qs[r]);
                 ++n_member;
                 if (ORDERED) n_absorb += (b1 >> 31) ^ 1u;
                 // emission-only records take the absorbing branch too: with
@@ -364,7 +420,7 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 // (exact), a in [1, 2 (i1 - i0) + 1] is the box test and
 // fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0) once, which is
 // the binary32 offset of the index recipe bit for bit.
-template <int T, bool ORDERED, bool KAHAN, bool COUNT>
+template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D>
 __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     constexpr int NT = T * T;
     constexpr int NW = NT / 64;  // 8x8 blocks per tile, one workgroup of one wave each
@@ -442,13 +498,14 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     fill();
     // the records of the next batch are in flight while a batch composites
     uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
+    uint32_t gidx = 0;
     auto gather = [&](uint32_t n) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if ((uint32_t)lane < n) {
-            const uint32_t idx = s_q[(head + lane) & (kQ - 1)];
-            ra = a.rec[idx].a;
-            rb = a.rec[idx].b;
+            gidx = s_q[(head + lane) & (kQ - 1)];
+            ra = a.rec[gidx].a;
+            rb = a.rec[gidx].b;
         }
         head += n;
         qn -= n;
@@ -457,7 +514,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     gather(ncur);
     while (ncur > 0) {
         if ((uint32_t)lane < ncur) {
-            const Expanded x = expand_loaded(a, ra, rb, s_vmin, s_vmax);
+            const Expanded x = expand_loaded(a, ra, rb, gidx, s_vmin, s_vmax);
             const int i0 = (int)(x.b0 & kBboxMask), i1 = (int)((x.b0 >> kBboxBits) & kBboxMask);
             const int j0 = (int)(x.b1 & kBboxMask), j1 = (int)((x.b1 >> kBboxBits) & kBboxMask);
             s_r[0][lane] = make_float4(x.ur, x.vr, x.r2, x.qs);
@@ -497,7 +554,7 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             const bool emit_only = (flags & kEmitOnly) != 0;
             if (!in) return;
             if (COUNT) ++n_member;
-            const float w = __builtin_amdgcn_exp2f(-d2 * f.w);  // exp(-q^2)
+            const float w = column_weight<K3D>(d2, f.z, f.w);
             if (!ORDERED || emit_only) {
                 composite<ORDERED, KAHAN>(true, w, e.x, e.y, e.z, 0.f, 0.f, 0.f, C0, C1, C2, K0,
                                           K1, K2, T0, T1, T2);
@@ -653,7 +710,8 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
                 if (!(d2 <= r2)) continue;
                 ++n_member;
                 if (ORDERED && !emit_only) ++n_absorb;
-                const float w = __builtin_amdgcn_exp2f(-d2 * qs);  // exp(-q^2)
+                const float w = a.kernel3d ? column_weight<true>(d2, r2, qs)
+                                           : column_weight<false>(d2, r2, qs);
                 const int o = state_index<T>(i - tx0, j - ty0);
                 float C0 = s_C[0][o], C1 = s_C[1][o], C2 = s_C[2][o];
                 float T0 = 1.f, T1 = 1.f, T2 = 1.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
@@ -782,15 +840,26 @@ __global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t
 template <int T, bool ORDERED, bool KAHAN>
 hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     switch (a.variant) {
-        case kSplatRows:
+        case kSplatRows: {
             // one single-wave workgroup per 8x8 block of every item
-            if (a.count)
-                hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true>),
-                                   dim3(grid * (T * T / 64)), dim3(64), 0, s, a);
-            else
-                hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false>),
-                                   dim3(grid * (T * T / 64)), dim3(64), 0, s, a);
+            const dim3 g(grid * (T * T / 64)), b(64);
+            if (a.kernel3d) {
+                if (a.count)
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true, true>), g, b, 0, s,
+                                       a);
+                else
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false, true>), g, b, 0,
+                                       s, a);
+            } else {
+                if (a.count)
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true, false>), g, b, 0,
+                                       s, a);
+                else
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false, false>), g, b, 0,
+                                       s, a);
+            }
             break;
+        }
         case kSplatLists:
             hipLaunchKernelGGL((k_splat_lists<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
                                a);

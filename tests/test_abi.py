@@ -136,7 +136,8 @@ def test_perspective_needs_positive_near_and_focal():
     (dict(sigma_over_h=0.0), 1), (dict(trunc_f=-1.0), 1), (dict(tile=12), 4), (dict(tile=64), 4),
     (dict(splat_variant=4), 1), (dict(splat_variant=-1), 1), (dict(splat_variant=3), 0),
     (dict(seg_records=-5), 1), (dict(batch_streams=5), 1), (dict(batch_streams=-1), 1),
-    (dict(batch_streams=4), 0),
+    (dict(batch_streams=4), 0), (dict(kernel=2), 1), (dict(kernel=-1), 1), (dict(kernel=1), 0),
+    (dict(emission_is_source=2), 1), (dict(emission_is_source=1), 0),
 ])
 def test_param_validation(kw, code):
     cam = B.camera_struct(synth.ortho_unit_square(64, 64))
@@ -146,7 +147,8 @@ def test_param_validation(kw, code):
 def test_species_validation():
     cam = B.camera_struct(synth.ortho_unit_square(64, 64))
     bad = [synth.Species(mode=5), synth.Species(absorption=-1.0),
-           synth.Species(vmin=-1.0, vmax=2.0, log_scale=1)]
+           synth.Species(vmin=-1.0, vmax=2.0, log_scale=1), synth.Species(colour=2),
+           synth.Species(colour=-1)]
     for s in bad:
         assert _ws_size(10, cam, B.params_struct([s]))[0] == 1
     p = B.params_struct([synth.Species()])
@@ -181,6 +183,16 @@ def test_render_rejects_before_launch():
     # palette with one entry, image of the wrong size
     bad_cm = B.Colourmap(1, C.c_void_p(0x1000))
     assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(bad_cm), C.byref(prm), C.byref(img)) == 1
+    # absorption table with one entry
+    bad_cm = B.Colourmap(256, C.c_void_p(0x1000), 1, C.c_void_p(0x3000))
+    assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(bad_cm), C.byref(prm), C.byref(img)) == 1
+    # a vector-coloured species without its second and third components
+    vec = B.params_struct([synth.Species(colour=synth.COLOUR_VECTOR)])
+    vec.workspace, vec.workspace_bytes = prm.workspace, prm.workspace_bytes
+    Pv = B.Particles()
+    Pv.n = 4
+    Pv.x = Pv.y = Pv.z = Pv.h = Pv.value = C.c_void_p(0x4000)
+    assert lib.splotch_render(C.byref(Pv), C.byref(cam), C.byref(cm), C.byref(vec), C.byref(img)) == 1
     bad_img = B.Image(C.c_void_p(0x2000), 32, 64)
     assert lib.splotch_render(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm), C.byref(bad_img)) == 1
     P.n = 1 << 32

@@ -29,8 +29,9 @@ def gpu_render(scene, img_in=None, **kw):
     if img_in is not None:
         image = torch.from_numpy(np.ascontiguousarray(img_in, np.float32)).cuda()
         kw["accumulate"] = True
-    out = B.render(parts, scene.camera, pal, scene.species_params, image,
-                   sigma_over_h=scene.sigma_over_h, trunc_f=scene.trunc_f, **kw)
+    opts = B.scene_options(scene)
+    opts.update(kw)
+    out = B.render(parts, scene.camera, pal, scene.species_params, image, **opts)
     st = None
     if isinstance(out, tuple):
         out, st = out
