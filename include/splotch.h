@@ -46,7 +46,9 @@ typedef enum {
     SPLOTCH_E_WORKSPACE = 2,   /* workspace missing or too small for n particles */
     SPLOTCH_E_DEVICE = 3,      /* a HIP runtime call failed */
     SPLOTCH_E_UNSUPPORTED = 4, /* valid but not supported (e.g. tile size) */
-    SPLOTCH_E_CAPACITY = 5     /* one particle needs more pair slots than the workspace holds */
+    SPLOTCH_E_CAPACITY = 5,    /* one particle needs more pair slots than the workspace holds */
+    SPLOTCH_E_SCRATCH = 6      /* splotch_render_static: the input needs more than the
+                                  library's static scratch buffer */
 } splotch_status;
 
 enum { SPLOTCH_ORTHO = 0, SPLOTCH_PERSPECTIVE = 1 };
@@ -257,6 +259,29 @@ splotch_status splotch_workspace_size(int64_t n, const splotch_camera *cam,
 splotch_status splotch_render(const splotch_particles *particles, const splotch_camera *cam,
                               const splotch_colourmap *cmap, const splotch_params *params,
                               splotch_image *image);
+
+/* Allocation-free render, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, result and errors as splotch_render, except
+ * that params->workspace and params->workspace_bytes are ignored: the
+ * workspace is a static device buffer of SPLOTCH_STATIC_SCRATCH_BYTES that
+ * the library holds on each GPU it runs on until the process ends (its
+ * address is looked up once per device, on the first call there).  The
+ * call allocates no device memory.
+ * Limits: the render's smallest workspace, splotch_workspace_size(n, cam,
+ * params, 1, ...), must fit in the buffer, else SPLOTCH_E_SCRATCH before
+ * any work is queued (about 4e6 particles at 1024x1024 with an ordered
+ * species); pairs beyond what the buffer holds are rendered in several
+ * passes, as with a small workspace.  params->profile must be 0 (stage
+ * timing creates events), else SPLOTCH_E_INVALID_ARG.
+ * Every call on one GPU uses that GPU's single buffer, which keeps the
+ * last call's contents (the render clears what it needs): calls that
+ * overlap on one GPU, from several host threads or on several streams,
+ * race and must be serialised by the caller. */
+#define SPLOTCH_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+splotch_status splotch_render_static(const splotch_particles *particles,
+                                     const splotch_camera *cam, const splotch_colourmap *cmap,
+                                     const splotch_params *params, splotch_image *image);
 
 /* Stage outputs for inspection and exact comparison (Section 3.2: the
  * screen transform and footprint of each particle).  For every particle

@@ -23,7 +23,7 @@ COLOUR_PALETTE, COLOUR_VECTOR = 0, 1
 KERNEL_GAUSS2D, KERNEL_TRUNC3D = 0, 1
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "device", 4: "unsupported",
-          5: "capacity"}
+          5: "capacity", 6: "scratch"}
 
 
 class SplotchError(RuntimeError):
@@ -95,7 +95,7 @@ class Image(C.Structure):
 _L = None
 
 EXPORTS = ("splotch_status_string", "splotch_camera_look_at", "splotch_workspace_size",
-           "splotch_render", "splotch_project", "splotch_bin", "splotch_render_batch",
+           "splotch_render", "splotch_render_static", "splotch_project", "splotch_bin", "splotch_render_batch",
            "splotch_graph_cache_clear", "splotch_nn_gemm", "splotch_nn_gemm_splits",
            "splotch_nn_im2col3x3", "splotch_nn_flip_weights", "splotch_nn_epilogue",
            "splotch_nn_conv3x3_weights", "splotch_nn_conv3x3",
@@ -125,6 +125,10 @@ def _lib():
         L.splotch_render.restype = C.c_int
         L.splotch_render.argtypes = [C.POINTER(Particles), C.POINTER(CameraS),
                                      C.POINTER(Colourmap), C.POINTER(Params), C.POINTER(Image)]
+        L.splotch_render_static.restype = C.c_int
+        L.splotch_render_static.argtypes = [C.POINTER(Particles), C.POINTER(CameraS),
+                                            C.POINTER(Colourmap), C.POINTER(Params),
+                                            C.POINTER(Image)]
         L.splotch_project.restype = C.c_int
         L.splotch_project.argtypes = [C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Params),
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -337,6 +341,36 @@ def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, 
         prm.stats = C.pointer(st)
     _check(_lib().splotch_render(C.byref(P), C.byref(cs), C.byref(cm), C.byref(prm),
                                  C.byref(img)), "splotch_render")
+    return (image, st.as_dict()) if stats else image
+
+
+def render_static(parts: dict, cam, palette, species, image, *, sigma_over_h=1.0, trunc_f=2.0,
+                  accumulate=False, compensated=False, tile=0, stats=False, seg_records=0,
+                  tile_mask=None, splat_variant=0, palette_absorb=None, kernel=KERNEL_GAUSS2D,
+                  emission_is_source=0):
+    """splotch_render_static: the render with the library's static scratch
+    buffer as its workspace (no device allocation anywhere in the call;
+    image must be given).  Returns the image, or (image, stats dict)."""
+    import torch
+    P = particles_struct(parts)
+    cs = cam if isinstance(cam, CameraS) else camera_struct(cam)
+    prm = params_struct(species, sigma_over_h=sigma_over_h, trunc_f=trunc_f,
+                        accumulate=accumulate, compensated=compensated, tile=tile,
+                        seg_records=seg_records, tile_mask=tile_mask,
+                        splat_variant=splat_variant, kernel=kernel,
+                        emission_is_source=emission_is_source)
+    dev = parts["x"].device
+    prm.stream = _stream_ptr(dev)
+    if image.dtype != torch.float32 or not image.is_contiguous() or \
+            tuple(image.shape) != (3, cs.height, cs.width):
+        raise ValueError("image must be contiguous float32 [3, H, W]")
+    cm = colourmap_struct(palette, palette_absorb)
+    img = Image(C.c_void_p(image.data_ptr()), cs.width, cs.height)
+    st = Stats()
+    if stats:
+        prm.stats = C.pointer(st)
+    _check(_lib().splotch_render_static(C.byref(P), C.byref(cs), C.byref(cm), C.byref(prm),
+                                        C.byref(img)), "splotch_render_static")
     return (image, st.as_dict()) if stats else image
 
 

@@ -750,6 +750,7 @@ const char *splotch_status_string(splotch_status s) {
         case SPLOTCH_E_DEVICE: return "HIP runtime error";
         case SPLOTCH_E_UNSUPPORTED: return "unsupported setting";
         case SPLOTCH_E_CAPACITY: return "a particle needs more pair slots than the workspace holds";
+        case SPLOTCH_E_SCRATCH: return "input needs more than the static scratch buffer holds";
     }
     return "unknown status";
 }

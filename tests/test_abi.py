@@ -246,3 +246,24 @@ def test_fused_conv_argument_checks():
     for args in bad:
         assert L.splotch_nn_conv3x3(*args, None) == 1, args  # SPLOTCH_E_INVALID_ARG
     assert L.splotch_nn_conv3x3_weights(None, p, 32, 32, None) == 1
+
+
+def test_static_render_refuses_before_device_work():
+    """splotch_render_static checks sizes and settings on the host: an input
+    beyond the static buffer and stage timing are refused before any HIP
+    call (no GPU here)."""
+    cam = B.camera_struct(synth.ortho_unit_square(4096, 4096))
+    P = B.Particles()
+    P.n = 100_000_000
+    P.x = P.y = P.z = P.h = P.value = C.c_void_p(0x1000)
+    cm = B.Colourmap(256, C.c_void_p(0x1000), 0, None)
+    img = B.Image(C.c_void_p(0x2000), 4096, 4096)
+    lib = B.lib()
+    prm = _params()
+    assert lib.splotch_render_static(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm),
+                                     C.byref(img)) == 6
+    prm.profile = 1
+    assert lib.splotch_render_static(C.byref(P), C.byref(cam), C.byref(cm), C.byref(prm),
+                                     C.byref(img)) == 1
+    assert "static scratch" in B.status_string(6)
+
