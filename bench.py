@@ -25,10 +25,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mparticles/s and frames/s at 4096² (1 GPU); learned vs plain at PSNR≥40dB"
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 78.6  # non-packed FP32 FMA rate: 256 CU x 64 lanes x 2 x 2.4 GHz
-# algorithmic FP32 operations per composited (pixel, particle) contribution
-FLOPS_EMISSION = 11   # weight (scale, exp) + per channel E*w, *T, +=
-FLOPS_ABSORBING = 29  # weight + per channel E*w, A*w, exp, 1-e, /x, *T*phi (2), +=, T*=
+# MI355X published FP32 vector peak (256 CUs x 2.4 GHz x 256 flops/clk, which
+# counts packed FP32 FMA); the kernels are built without packed FP32, so
+# the unpacked FMA rate (256 CU x 64 lanes x 2 x 2.4 GHz) is given beside it
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_FMA_UNPACKED_TFLOPS = 78.6
+# algorithmic FP32 operations per composited (pixel, particle) contribution:
+# emission only, about 10 flops (weight: scale and exp; per channel E w, and
+# T E w) plus 1 exp and 12 for the compensated add of three channels;
+# absorbing, about 25 flops plus 4 exp (weight and three transmittances)
+FLOPS_EMISSION = 23
+FLOPS_ABSORBING = 29
 
 
 SPLAT_KERNELS = {0: "k_splat_rows", 1: "k_splat_rows", 2: "k_splat_lists", 3: "k_splat_box"}
@@ -95,27 +102,85 @@ def make_workload(args, torch):
     return parts, cam, sp, pal, cfg
 
 
-def cpu_baseline(parts, cam, sp, args, np, torch):
-    """The FP64 oracle on a seeded random subsample of the same particles
-    (same smoothing lengths, same camera and image size), single thread."""
-    import oracle
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_scene(parts, cam, sp, idx=None):
+    """Host copy of (a subset of) the device particles as an oracle scene."""
     from paper_1004_1302_amd import synth
+    pick = (lambda t: t[idx]) if idx is not None else (lambda t: t)
+    host = {key: pick(t).cpu().numpy() for key, t in parts.items()}
+    return synth.Scene(host["x"], host["y"], host["z"], host["h"], host["value"], cam, sp,
+                       species=host.get("species"), rho0=host.get("rho0"))
+
+
+def cpu_baseline(parts, cam, sp, args, np, torch):
+    """The FP64 oracle timed on the host cores: row bands of the image
+    painted by all OpenMP threads (the same image as the single-thread
+    definition, bit for bit).  Sets above 1e7 particles are timed on a
+    seeded random subsample (--cpu-fraction, default 1/1000: the full set
+    in FP64 does not fit host memory) and the per-particle rate is
+    extrapolated; smaller sets are timed whole."""
+    import oracle
     n = int(parts["x"].numel())
-    k = min(n, int(args.cpu_sample))
-    gen = torch.Generator(device="cpu")
-    gen.manual_seed(17)
-    idx = torch.unique(torch.randint(0, n, (k,), generator=gen)).to(parts["x"].device)
-    k = int(idx.numel())
-    host = {key: t[idx].cpu().numpy() for key, t in parts.items()}
-    scene = synth.Scene(host["x"], host["y"], host["z"], host["h"], host["value"], cam, sp,
-                        species=host.get("species"), rho0=host.get("rho0"))
+    frac = 1.0 if n <= 10_000_000 else float(args.cpu_fraction)
+    k = max(1, int(round(n * frac)))
+    if k < n:
+        gen = torch.Generator(device="cpu")
+        gen.manual_seed(17)
+        idx = torch.unique(torch.randint(0, n, (k,), generator=gen)).to(parts["x"].device)
+        k = int(idx.numel())
+        scene = host_scene(parts, cam, sp, idx)
+    else:
+        scene = host_scene(parts, cam, sp)
     oracle.lib()
+    threads = oracle.threads()
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.render_rows(scene, band=16)
+        runs.append(time.perf_counter() - t0)
+    dt = float(np.median(runs))
+    what = (f"seeded random subsample of {k} of {n} particles (1/{round(n / k)}), rate "
+            f"extrapolated per particle" if k < n else f"all {n} particles")
+    return dict(value=round(k / dt / 1e6, 6), unit="Mparticles/s", cores=threads, kind="oracle",
+                nproc=os.cpu_count(), cpu_model=cpu_model(), extrapolated=k < n,
+                sample=f"{what}; same camera and {cam.width}x{cam.height} image; FP64, row "
+                       f"bands on {threads} OpenMP threads; median of 3 runs, {dt:.2f} s each")
+
+
+def sampled_error(parts, cam, sp, image, np, n_random=1984, n_top=64):
+    """Oracle check of the timed frame on sampled pixels (the brightest plus
+    random ones), each evaluated by the oracle over every particle.
+    Returns the relative L-infinity error per channel (normalised by the
+    largest sampled oracle value) and the largest per-pixel relative error
+    with an absolute floor of 1e-6 of that value."""
+    import oracle
+    img = image.cpu().numpy()
+    H, W = img.shape[1:]
+    rng = np.random.default_rng(0)
+    flat = img.sum(0).ravel()
+    pix = np.concatenate([np.argsort(flat)[-n_top:], rng.integers(0, flat.size, n_random)])
+    pj, pi = np.unravel_index(pix, (H, W))
+    scene = host_scene(parts, cam, sp)
     t0 = time.perf_counter()
-    oracle.render(scene)
+    ref = oracle.render_pixels(scene, pi, pj)
     dt = time.perf_counter() - t0
-    return dict(value=round(k / dt / 1e6, 6), unit="Mparticles/s", cores=1, kind="oracle",
-                sample=f"seeded random subsample of {k} of {n} particles, same camera and "
-                       f"{cam.width}x{cam.height} image, FP64 single thread, {dt:.2f} s")
+    got = img[:, pj, pi].T.astype(np.float64)
+    scale = np.abs(ref).max(axis=0)
+    scale = np.where(scale > 0, scale, 1.0)
+    rel = np.abs(got - ref).max(axis=0) / scale
+    per_px = (np.abs(got - ref) / (np.abs(ref) + 1e-6 * scale)).max(axis=0)
+    return dict(pixels=int(pix.size), rel_linf_per_channel=[float(f"{v:.3e}") for v in rel],
+                per_pixel_rel_max=[float(f"{v:.3e}") for v in per_px],
+                per_pixel_floor="1e-6 of the largest sampled value", oracle_seconds=round(dt, 1))
 
 
 def main():
@@ -124,7 +189,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal",
-                    choices=["lognormal", "nfw", "plummer", "learned", "batch"])
+                    choices=["lognormal", "nfw", "plummer", "learned", "batch", "copy", "split"])
+    ap.add_argument("--copy-mib", type=int, default=2048)
     ap.add_argument("--views", type=int, default=32)
     ap.add_argument("--batch-set", default="nfw", choices=["nfw", "plummer"])
     ap.add_argument("--train-pairs", type=int, default=2000)
@@ -135,8 +201,9 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--splat-variant", type=int, default=0)
     ap.add_argument("--max-pairs", type=float, default=0)
-    ap.add_argument("--cpu-sample", type=float, default=5_000_000)
+    ap.add_argument("--cpu-fraction", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the renderer "
@@ -152,6 +219,10 @@ def main():
         return learned_leg(args, np, torch)
     if args.workload == "batch":
         return batch_leg(args, np, torch)
+    if args.workload == "copy":
+        return copy_leg(args, torch)
+    if args.workload == "split":
+        return split_leg(args, np, torch)
 
     t0 = time.perf_counter()
     parts, cam, sp, pal, cfg = make_workload(args, torch)
@@ -183,13 +254,17 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     log(f"timed {args.steps} steps: {ms:.3f} ms/step")
 
-    # per-stage breakdown with the library's own HIP events
+    # per-stage breakdown with the library's own HIP events, from frames
+    # that run the same kernels as the timed ones (profile level 1), then
+    # one frame that also counts the composited (pixel, particle) pairs
+    # (profile level 2: the splat's counting variant)
     stage_runs = []
     for s in range(max(1, min(args.steps, 5))):
-        _, st = step(profile=True)
+        _, st = step(profile=1)
         stage_runs.append(st)
-    st = stage_runs[-1]
-    stages = {k: float(np.mean([r["stage_ms"][k] for r in stage_runs])) for k in st["stage_ms"]}
+    stages = {k: float(np.mean([r["stage_ms"][k] for r in stage_runs]))
+              for k in stage_runs[0]["stage_ms"]}
+    _, st = step(profile=2)
     dominant = max(stages, key=stages.get)
     log(f"stages ms: {json.dumps({k: round(v, 3) for k, v in stages.items()})}")
     n_mem, n_abs = st["n_member_pairs"], st["n_member_absorbing"]
@@ -202,7 +277,11 @@ def main():
         roof = dict(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
                     traffic=measured_traffic(kern, cfg, args), kernel=kern,
-                    member_pairs=n_mem, member_pairs_absorbing=n_abs)
+                    kernel_ms=round(stages["splat"], 3), flops_per_launch=flops,
+                    flops_per_pair=dict(emission_only=FLOPS_EMISSION, absorbing=FLOPS_ABSORBING),
+                    member_pairs=n_mem, member_pairs_absorbing=n_abs,
+                    peak_fma_unpacked=FP32_FMA_UNPACKED_TFLOPS,
+                    frac_fma_unpacked=round(ach / FP32_FMA_UNPACKED_TFLOPS, 4))
     else:
         algo_bytes = {
             "project": n * (24 + 4 + 1) + st["n_visible"] * 32 + n * 8,
@@ -234,10 +313,105 @@ def main():
         "stages_ms": {k: round(v, 3) for k, v in stages.items()},
         "roofline": roof,
     }
+    if not args.no_check:
+        log("oracle check of the timed frame on sampled pixels ...")
+        out["parity"] = sampled_error(parts, cam, sp, image, np)
+        log(f"parity: {out['parity']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(parts, cam, sp, args, np, torch)
     print(json.dumps(out), flush=True)
+    # hand the device memory back before the process ends
+    del parts, image
+    B.release_workspace()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def split_leg(args, np, torch):
+    """Split particles (Section 3.2, Table 2): NFW halo sets of the three
+    sizes of the paper's table (370,852, 2,646,991 and 16,202,527 particles)
+    seen from inside the box at 1920x1080, so that footprints range from a
+    pixel to the whole window.  For each set: frame time and the pair
+    emission stage with splitting off, at the paper's threshold (W+H)/2 =
+    1500 pixels, and at other thresholds (median of --steps frames each)."""
+    from paper_1004_1302_amd import binding as B
+    from paper_1004_1302_amd import synth
+    W, H = 1920, 1080
+    cam = synth.look_at((50.0, 50.0, 10.0), (50.0, 50.0, 60.0), (0.0, 1.0, 0.0),
+                        synth.PERSPECTIVE, W, H, z_near=0.5, z_far=500.0)
+    thresholds = [-1, 64, 256, (W + H) // 2, 4096, 16384, 65536]
+    sets = []
+    for name, n in (("small", 370_852), ("medium", 2_646_991), ("large", 16_202_527)):
+        sc = synth.nfw_halos(n, seed=2)
+        parts, pal = B.scene_to_device(sc, "cuda:0")
+        sp = sc.species_params
+        image = torch.empty((3, H, W), dtype=torch.float32, device="cuda:0")
+        rows = {}
+        ref = None
+        for thr in thresholds:
+            kw = dict(compensated=True, split_pixels=thr)
+            B.render(parts, cam, pal, sp, image, **kw)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = image.clone()
+            elif not torch.equal(image, ref):
+                raise SystemExit(f"split threshold {thr} changed the image")
+            frame, emit = [], []
+            for _ in range(max(3, args.steps)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                B.render(parts, cam, pal, sp, image, **kw)
+                e1.record()
+                _, st = B.render(parts, cam, pal, sp, image, profile=1, **kw)
+                torch.cuda.synchronize()
+                frame.append(e0.elapsed_time(e1))
+                emit.append(st["stage_ms"]["emit"])
+            rows[str(thr)] = dict(frame_ms=round(float(np.median(frame)), 3),
+                                  emit_ms=round(float(np.median(emit)), 3))
+        _, st = B.render(parts, cam, pal, sp, image, stats=True, compensated=True)
+        del parts, image
+        B.release_workspace()
+        torch.cuda.empty_cache()
+        sets.append(dict(set=name, n_particles=n, pairs=st["n_pairs"], timings=rows,
+                         split_vs_none_frame=round(rows[str((W + H) // 2)]["frame_ms"] /
+                                                   rows["-1"]["frame_ms"], 4),
+                         split_vs_none_emit=round(rows[str((W + H) // 2)]["emit_ms"] /
+                                                  rows["-1"]["emit_ms"], 4)))
+        log(f"split: {name} {json.dumps(rows)}")
+    out = {"metric": "frame ms with and without split particles", "value":
+           sets[-1]["timings"][str((W + H) // 2)]["frame_ms"], "unit": "ms (large set, (W+H)/2)",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": dict(workload="split_particles", width=W, height=H,
+                          camera="inside the NFW box, 60 deg", thresholds_px=thresholds,
+                          paper_threshold_px=(W + H) // 2),
+           "sets": sets}
+    print(json.dumps(out), flush=True)
+
+
+def copy_leg(args, torch):
+    """Plain device-to-device copies of --copy-mib MiB: the achieved
+    streaming rate (read + write) the HBM-bound passes are compared with,
+    and, run under `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE), the
+    known bytes that calibrate those counters."""
+    n = args.copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # first touch
+    torch.cuda.synchronize()
+    reps = max(3, args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
+        dst.copy_(src)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+    best = min(ms)
+    print(json.dumps({"metric": "device copy bandwidth (read + write)",
+                      "value": round(2 * n * 4 / (best * 1e-3) / 1e12, 3), "unit": "TB/s",
+                      "copy_bytes_read": n * 4, "copy_bytes_written": n * 4,
+                      "dispatches": reps + 1, "ms": [round(m, 4) for m in ms]}), flush=True)
 
 
 def batch_leg(args, np, torch):
@@ -338,26 +512,36 @@ def batch_leg(args, np, torch):
 
 
 def learned_leg(args, np, torch):
-    """Learned decimation against the plain render: 20M particles of the
-    Plummer-mix generator, square images of --size px from cameras on a
-    seeded orbit; the network trains on pairs the renderer makes on the fly
-    (--train-pairs views, 4 per step) and is evaluated on --test-views
-    held-out views (tone-mapped PSNR, max error), with frame times of the
-    learned path (decimated render + network + probe) and of the full
+    """Learned decimation against the plain render: particle sets of the
+    Plummer-mix generator (20M particles each), square images of --size px
+    from cameras on a seeded orbit.  The network trains on pairs the
+    renderer makes on the fly (--train-pairs views, 4 per step) from four
+    particle sets, each with its own generator and decimation seed, and is
+    evaluated on --test-views held-out views of one of those sets (seen)
+    and of a fifth set whose seeds training never saw (unseen):
+    tone-mapped PSNR, max error, fallback rate at 40 dB, and frame times of
+    the learned path (decimated render + network + probe) and of the full
     render."""
     from paper_1004_1302_amd import binding as B
     from paper_1004_1302_amd import learned as LN
     from paper_1004_1302_amd import synth
     n = int(args.n or 20_000_000)
     t0 = time.perf_counter()
-    sc = synth.plummer_mix(n, seed=5)
-    parts, pal = B.scene_to_device(sc, "cuda:0")
-    dec = LN.decimate(parts, seed=6)
-    sp = sc.species_params
+
+    def particle_set(seed):
+        sc = synth.plummer_mix(n, seed=seed)
+        parts, pal = B.scene_to_device(sc, "cuda:0")
+        return parts, LN.decimate(parts, seed=seed + 1), pal, sc.species_params
+
+    train_sets = [particle_set(sd) for sd in (5, 15, 25, 35)]
+    unseen = particle_set(45)
+    pal, sp = train_sets[0][2], train_sets[0][3]
     size = args.size
-    cams = synth.orbit_cameras(args.train_pairs + args.test_views, 9, [(size, size)])
-    train, test = cams[:args.train_pairs], cams[args.train_pairs:]
-    log(f"learned: {n} particles ({int(dec['x'].numel())} decimated) in "
+    cams = synth.orbit_cameras(args.train_pairs + 2 * args.test_views, 9, [(size, size)])
+    train = cams[:args.train_pairs]
+    test_seen = cams[args.train_pairs:args.train_pairs + args.test_views]
+    test_unseen = cams[args.train_pairs + args.test_views:]
+    log(f"learned: 5 sets of {n} particles ({int(unseen[1]['x'].numel())} decimated) in "
         f"{time.perf_counter() - t0:.1f} s")
     net = LN.UNet(seed=0)
     rec = LN.Reconstructor(net)
@@ -366,6 +550,7 @@ def learned_leg(args, np, torch):
     batch = 4
     steps = max(1, len(train) // batch)
     for it in range(steps):
+        parts, dec = train_sets[it % len(train_sets)][:2]
         views = train[it * batch:(it + 1) * batch]
         d = [B.render(dec, c, pal, sp, **kw).clone() for c in views]
         f = [B.render(parts, c, pal, sp, **kw).clone() for c in views]
@@ -376,46 +561,59 @@ def learned_leg(args, np, torch):
             log(f"train step {it + 1}/{steps} loss {loss:.3e}")
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
-    psnr_net, psnr_dec, maxerr, fb = [], [], [], 0
-    ev = lambda: torch.cuda.Event(enable_timing=True)
-    t_learn, t_full = [], []
-    for c in test:
-        e0, e1, e2 = ev(), ev(), ev()
-        e0.record()
-        full = B.render(parts, c, pal, sp, **kw)
-        e1.record()
-        img, info = LN.render_learned(parts, dec, c, pal, sp, rec, threshold_db=40.0, **kw)
-        e2.record()
-        torch.cuda.synchronize()
-        t_full.append(e0.elapsed_time(e1))
-        t_learn.append(e1.elapsed_time(e2))
-        d = B.render(dec, c, pal, sp, **kw)
-        out = rec.infer(d)
-        torch.cuda.synchronize()
-        fh, oh, dh = full.cpu().numpy(), out.cpu().numpy(), d.cpu().numpy()
-        psnr_net.append(LN.psnr_tonemapped(oh, fh))
-        psnr_dec.append(LN.psnr_tonemapped(dh, fh))
-        maxerr.append(float(np.abs(oh - fh).max() / max(np.abs(fh).max(), 1e-30)))
-        fb += int(info["fallback"])
-    med = lambda a: float(np.median(a))
+
+    def evaluate(pset, views):
+        parts, dec = pset[:2]
+        psnr_net, psnr_dec, maxerr, fb = [], [], [], 0
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+        t_learn, t_full = [], []
+        for c in views:
+            e0, e1, e2 = ev(), ev(), ev()
+            e0.record()
+            full = B.render(parts, c, pal, sp, **kw)
+            e1.record()
+            img, info = LN.render_learned(parts, dec, c, pal, sp, rec, threshold_db=40.0, **kw)
+            e2.record()
+            torch.cuda.synchronize()
+            t_full.append(e0.elapsed_time(e1))
+            t_learn.append(e1.elapsed_time(e2))
+            d = B.render(dec, c, pal, sp, **kw)
+            out = rec.infer(d)
+            torch.cuda.synchronize()
+            fh, oh, dh = full.cpu().numpy(), out.cpu().numpy(), d.cpu().numpy()
+            psnr_net.append(LN.psnr_tonemapped(oh, fh))
+            psnr_dec.append(LN.psnr_tonemapped(dh, fh))
+            maxerr.append(float(np.abs(oh - fh).max() / max(np.abs(fh).max(), 1e-30)))
+            fb += int(info["fallback"])
+        med = lambda a: float(np.median(a))
+        return {
+            "psnr_net_median_db": round(med(psnr_net), 3),
+            "psnr_decimated_median_db": round(med(psnr_dec), 3),
+            "psnr_gain_median_db": round(med(np.array(psnr_net) - np.array(psnr_dec)), 3),
+            "max_rel_error_median": round(med(maxerr), 5),
+            "fallback_rate_at_40db": fb / len(views),
+            "ms_full_render_median": round(med(t_full), 3),
+            "ms_learned_path_median": round(med(t_learn), 3),
+        }
+
+    seen = evaluate(train_sets[0], test_seen)
+    new = evaluate(unseen, test_unseen)
     out = {
         "metric": METRIC,
-        "value": round(med(psnr_net), 3),
-        "unit": "dB (tone-mapped PSNR of the learned reconstruction vs the full render)",
+        "value": new["psnr_net_median_db"],
+        "unit": "dB (tone-mapped PSNR of the learned reconstruction vs the full render, "
+                "particle set unseen in training)",
         "higher_is_better": True,
         "n_gpus": 1,
         "dtype": "bf16 network, f32 render",
         "data": "synthetic",
         "config": dict(workload="learned_decimation", n_particles=n, decimation=LN.DECIMATE,
-                       width=size, height=size, train_pairs=len(train), test_views=len(test),
+                       width=size, height=size, train_pairs=len(train),
+                       train_sets="generator seeds 5, 15, 25, 35 (decimation seed + 1)",
+                       test_views=len(test_unseen), unseen_set="generator seed 45",
                        params=net.n_params(), levels=list(LN.LEVELS)),
-        "psnr_net_median_db": round(med(psnr_net), 3),
-        "psnr_decimated_median_db": round(med(psnr_dec), 3),
-        "psnr_gain_median_db": round(med(np.array(psnr_net) - np.array(psnr_dec)), 3),
-        "max_rel_error_median": round(med(maxerr), 5),
-        "fallback_rate_at_40db": fb / len(test),
-        "ms_full_render_median": round(med(t_full), 3),
-        "ms_learned_path_median": round(med(t_learn), 3),
+        "unseen_set": new,
+        "seen_set_new_views": seen,
         "train_seconds": round(train_s, 1),
     }
     print(json.dumps(out), flush=True)

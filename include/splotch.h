@@ -162,8 +162,9 @@ typedef struct splotch_stats {
      * measured with HIP events on params->stream and summed over chunks:
      * [0] value range + projection, [1] depth sort + reorder,
      * [2] pair-offset scan, [3] pair emission, [4] tile sort + ranges,
-     * [5] splat; the number of (pixel, particle) contributions the splat
-     * composited, and how many of them came from absorbing particles. */
+     * [5] splat.  With profile = 2 also the number of (pixel, particle)
+     * contributions the splat composited and how many of them came from
+     * absorbing particles (the splat then runs its counting variant). */
     float stage_ms[6];
     int64_t n_member_pairs;
     int64_t n_member_absorbing;
@@ -179,7 +180,9 @@ typedef struct splotch_params {
                            the light entering from behind every particle) */
     int32_t compensated; /* 1: compensated (Kahan) summation of emission */
     int32_t tile;        /* tile edge in pixels: 0 (= 16), 8, 16 or 32 */
-    int32_t profile;     /* 1: time each stage (needs stats) */
+    int32_t profile;     /* 1: time each stage (needs stats); 2: also count the
+                            composited contributions; other values:
+                            SPLOTCH_E_INVALID_ARG */
     int32_t seg_records; /* least records per tile-list segment (one workgroup
                             each); 0 = 1024.  Long lists are cut into segments
                             whose partial (C, T) are merged front to back:
@@ -220,6 +223,14 @@ typedef struct splotch_params {
                             Eq. (1) runs with E := A * E, and the update is
                             I <- (I - E) exp(-A tau) + E.  ADDITIVE species
                             are unaffected. */
+    int32_t split_pixels; /* split particles (Section 3.2): a particle whose
+                            footprint box covers more pixels than this has
+                            its (tile, particle) pairs written by a whole
+                            workgroup instead of one thread.  0 = (W + H) / 2
+                            of the camera, the paper's suggestion; < 0 =
+                            never.  Speed only: the pairs and the image are
+                            the same bits either way (not used with a
+                            tile_mask). */
 } splotch_params;
 
 /* Output image: planar float32 [3][height][width], device. */
@@ -280,6 +291,37 @@ splotch_status splotch_render(const splotch_particles *particles, const splotch_
  * race and must be serialised by the caller. */
 #define SPLOTCH_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
 splotch_status splotch_render_static(const splotch_particles *particles,
+                                     const splotch_camera *cam, const splotch_colourmap *cmap,
+                                     const splotch_params *params, splotch_image *image);
+
+/* Out-of-core render (Section 3.2: the subset loop that renders one part of
+ * the data while the fragments of the previous parts are combined; here
+ * the combination happens on the device).  host: the particle set in host
+ * memory (the same fields as splotch_particles, host pointers; pinned
+ * memory lets the copies overlap the work); n may exceed 2^32.  The set is
+ * copied to the device `subset` particles at a time, on a library-owned
+ * stream (default priority), into two staging buffers, overlapped with the
+ * work on params->stream.
+ *   - Additive-only sets: each subset is rendered and added into the image.
+ *   - With an ORDERED species: a first pass projects every subset and
+ *     histograms the depth keys (top 20 bits of the binary32 depth image,
+ *     i.e. bins 2^-11 of the depth wide); slabs are runs of bins holding at
+ *     most `slab` particles; from the farthest slab to the nearest, every
+ *     subset is projected again, its particles in the slab are gathered (in
+ *     index order) into a device buffer and the slab is rendered over the
+ *     image (C + T I_in).  The result equals splotch_render of the whole set
+ *     up to rounding (the composite is associative); the whole set is read
+ *     once per slab.  A depth bin with more than `slab` particles gives
+ *     SPLOTCH_E_CAPACITY.
+ * Automatic value ranges are those of the whole set (found in the first
+ * pass).  params->workspace: splotch_stream_workspace_size bytes (device,
+ * 256-aligned); params->tile_mask must be NULL.  stats (optional): counts
+ * over the whole set, n_pairs and n_chunks (renders) summed.  Returns after
+ * the last render is queued (the renders read back their pair totals). */
+splotch_status splotch_stream_workspace_size(const splotch_particles *host, int64_t subset,
+                                             int64_t slab, const splotch_camera *cam,
+                                             const splotch_params *params, size_t *bytes);
+splotch_status splotch_render_stream(const splotch_particles *host, int64_t subset, int64_t slab,
                                      const splotch_camera *cam, const splotch_colourmap *cmap,
                                      const splotch_params *params, splotch_image *image);
 
@@ -448,6 +490,134 @@ splotch_status splotch_nn_untonemap(const float *in, int32_t h, int32_t w, float
 
 /* float32 -> bfloat16 (round to nearest even). */
 splotch_status splotch_nn_f32_to_bf16(const float *in, uint16_t *out, int64_t n, void *stream);
+
+/* ------------------------------------------------------------------------
+ * The reconstruction network as an object.  n_levels levels with
+ * channels[l] features each (multiples of 32, <= 256); each level applies
+ * two 3x3 convolutions with ReLU; the encoder halves the resolution with
+ * 2x2 average pooling, the decoder doubles it with nearest upsampling and
+ * concatenates the encoder features of the same level; a last 3x3
+ * convolution (no activation) adds a correction to the tone-mapped input:
+ *   x = log1p(I_dec / s),  y = x + net(x),  I = s expm1(y),
+ * s = the mean of the decimated render (found on the device).  in_channels
+ * (a multiple of 32) carries the three tone-mapped colours, the rest zero.
+ * Weights live in caller-owned device memory of splotch_nn_param_bytes
+ * (FP32 master weights and biases, their gradients, Adam moments, BF16
+ * copies); activations in a caller-owned workspace of
+ * splotch_nn_workspace_bytes for the batch shape (n images of h x w, h and
+ * w multiples of 2^(n_levels-1)).  The object itself is host memory; it is
+ * not thread-safe.  All device work is asynchronous on `stream` except
+ * create, save and load, which wait for their copies.
+ * ------------------------------------------------------------------------ */
+#define SPLOTCH_NN_MAX_LEVELS 8
+typedef struct splotch_nn splotch_nn;
+typedef struct splotch_nn_config {
+    int32_t n_levels;
+    int32_t channels[SPLOTCH_NN_MAX_LEVELS];
+    int32_t in_channels;
+} splotch_nn_config;
+/* Where layer k keeps its tensors, as byte offsets: w, b, gw, gb (float32)
+ * and w_bf16 into the parameter memory; x (its bf16 input), y (its output:
+ * bf16, float32 for the last layer), dy and dx (float32 gradients of its
+ * output and input; dx = SIZE_MAX for the first layer, which has none) into
+ * the workspace laid out for the (n, h, w) given to splotch_nn_layer_info.
+ * Layers are ordered: encoder levels top down (two each), decoder levels
+ * from the deepest up (two each), then the output layer.  Weights are laid
+ * out [tap][cin][cout], taps (ky, kx) row-major; level l runs at h >> l. */
+typedef struct splotch_nn_layer {
+    int32_t cin, cout, relu, level;
+    size_t w, b, gw, gb, w_bf16;
+    size_t x, y, dy, dx;
+} splotch_nn_layer;
+
+splotch_status splotch_nn_param_bytes(const splotch_nn_config *cfg, size_t *bytes);
+/* Initialise the network in `params` (256-byte aligned): He-normal weights
+ * from a seeded generator (the output layer scaled by 0.1), zero biases and
+ * Adam moments, step 0. */
+splotch_status splotch_nn_create(const splotch_nn_config *cfg, void *params, size_t params_bytes,
+                                 uint64_t seed, void *stream, splotch_nn **net);
+splotch_status splotch_nn_destroy(splotch_nn *net);
+int32_t splotch_nn_n_layers(const splotch_nn *net);
+int32_t splotch_nn_get_step(const splotch_nn *net);
+splotch_status splotch_nn_workspace_bytes(splotch_nn *net, int32_t n, int32_t h, int32_t w,
+                                          size_t *bytes);
+splotch_status splotch_nn_layer_info(splotch_nn *net, int32_t k, int32_t n, int32_t h, int32_t w,
+                                     splotch_nn_layer *out);
+/* Network on tone-mapped NHWC input [n][h][w][in_channels] (x_f32 is the
+ * residual, x_bf16 the first convolution's input); y (may be NULL) receives
+ * the float32 output of the same shape.  Keeps the activations in the
+ * workspace for splotch_nn_backward. */
+splotch_status splotch_nn_forward(splotch_nn *net, const float *x_f32, const uint16_t *x_bf16,
+                                  int32_t n, int32_t h, int32_t w, float *y, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+/* Mean squared error over the three colour channels of y against target
+ * (both [n][h][w][in_channels]) and its gradient; loss_partials (256 floats)
+ * sum to the squared-error total. */
+splotch_status splotch_nn_loss_grad(splotch_nn *net, const float *y, const float *target,
+                                    int32_t n, int32_t h, int32_t w, float *grad,
+                                    float *loss_partials, void *stream);
+/* Gradients of every weight and bias for the output gradient grad_y, from
+ * the activations the last splotch_nn_forward left in the workspace. */
+splotch_status splotch_nn_backward(splotch_nn *net, const float *grad_y, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8, bias-corrected) on every layer;
+ * refreshes the BF16 copies. */
+splotch_status splotch_nn_adam_step(splotch_nn *net, float lr, void *stream);
+/* Training checkpoint: configuration, step, seed, FP32 weights, biases and
+ * Adam moments (host file, little-endian binary).  load requires the same
+ * configuration and resumes from the stored step. */
+splotch_status splotch_nn_save(const splotch_nn *net, const char *path, void *stream);
+splotch_status splotch_nn_load(splotch_nn *net, const char *path, void *stream);
+/* Image level: tone map the planar [3][h][w] decimated render with its own
+ * mean, run the network, map back into out_img (may equal dec_img). */
+splotch_status splotch_nn_reconstruct(splotch_nn *net, const float *dec_img, int32_t h, int32_t w,
+                                      float *out_img, void *workspace, size_t workspace_bytes,
+                                      void *stream);
+/* One training step on n (decimated, full) render pairs: dec_imgs and
+ * full_imgs are host arrays of n device pointers to planar [3][h][w]
+ * images; both are tone-mapped with the decimated render's mean; forward,
+ * loss, backward, Adam.  loss_partials: NULL or 256 device floats. */
+splotch_status splotch_nn_train_step(splotch_nn *net, const float *const *dec_imgs,
+                                     const float *const *full_imgs, int32_t n, int32_t h,
+                                     int32_t w, float lr, float *loss_partials, void *workspace,
+                                     size_t workspace_bytes, void *stream);
+
+/* Decimation: an exact seeded subset of m = max(1, n / keep) particles (a
+ * keyed permutation of the indices; kept particles in index order), with h
+ * and rho0 multiplied by keep^(1/3) (rho0 = keep^(1/3) where in->rho0 is
+ * NULL), which keeps the expected flux, proportional to rho0 sigma^2 per
+ * particle.  out holds caller-allocated device arrays of out->n = m
+ * elements: x, y, z, h, value, rho0, and species / value_g / value_b when
+ * the input has them.  workspace: splotch_decimate_workspace_bytes(n). */
+size_t splotch_decimate_workspace_bytes(int64_t n);
+splotch_status splotch_decimate(const splotch_particles *in, int32_t keep, uint64_t seed,
+                                splotch_particles *out, void *workspace, size_t workspace_bytes,
+                                void *stream);
+/* Probe tiles: mask (device, one byte per tile of `tile` px, row-major) = 1
+ * for a seeded sample of about frac of the tiles (at least one). */
+splotch_status splotch_probe_mask(int32_t width, int32_t height, int32_t tile, float frac,
+                                  uint64_t seed, uint8_t *mask, void *stream);
+splotch_status splotch_learned_workspace_bytes(splotch_nn *net, int32_t width, int32_t height,
+                                               int32_t tile, size_t *bytes);
+/* Learned decimated render with fallback.  Renders `dec` (the decimated
+ * set, tiles of dec_tile px; 0 = 16) into image, replaces it in place by the
+ * network's reconstruction, and renders `full` on the probe tiles of
+ * probe_mask (tiles of params->tile px) on a library-owned stream while the
+ * network runs.  The PSNR of the reconstruction against that probe, after
+ * the tone map T(I) = log1p(I/s) / log1p(max/s) with s the probe's mean,
+ * is computed on the device and returned in *probe_psnr (+inf when they
+ * agree exactly or the probe is dark); below psnr_threshold the full render
+ * replaces the image and *used_fallback = 1.  params: render settings,
+ * stream and a workspace that fits both renders; params->tile_mask must be
+ * NULL.  nn_workspace: splotch_learned_workspace_bytes.  Waits for the
+ * probe PSNR (one value read back). */
+splotch_status splotch_render_learned(const splotch_particles *full,
+                                      const splotch_particles *dec, const splotch_camera *cam,
+                                      const splotch_colourmap *cmap, const splotch_params *params,
+                                      int32_t dec_tile, splotch_nn *net, void *nn_workspace,
+                                      size_t nn_workspace_bytes, const uint8_t *probe_mask,
+                                      float psnr_threshold, splotch_image *image,
+                                      int32_t *used_fallback, float *probe_psnr);
 
 #ifdef __cplusplus
 }

@@ -85,7 +85,8 @@ class Params(C.Structure):
                 ("tile_mask", C.c_void_p),
                 ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats)),
-                ("kernel", C.c_int32), ("emission_is_source", C.c_int32)]
+                ("kernel", C.c_int32), ("emission_is_source", C.c_int32),
+                ("split_pixels", C.c_int32)]
 
 
 class Image(C.Structure):
@@ -102,7 +103,14 @@ EXPORTS = ("splotch_status_string", "splotch_camera_look_at", "splotch_workspace
            "splotch_nn_relu_bwd", "splotch_nn_colsum", "splotch_nn_pool2", "splotch_nn_pool2_bwd",
            "splotch_nn_up2_concat", "splotch_nn_up2_concat_bwd", "splotch_nn_mse",
            "splotch_nn_adam", "splotch_nn_tonemap", "splotch_nn_untonemap",
-           "splotch_nn_f32_to_bf16")
+           "splotch_nn_f32_to_bf16", "splotch_nn_param_bytes", "splotch_nn_create",
+           "splotch_nn_destroy", "splotch_nn_n_layers", "splotch_nn_get_step",
+           "splotch_nn_workspace_bytes", "splotch_nn_layer_info", "splotch_nn_forward",
+           "splotch_nn_loss_grad", "splotch_nn_backward", "splotch_nn_adam_step",
+           "splotch_nn_save", "splotch_nn_load", "splotch_nn_reconstruct",
+           "splotch_nn_train_step", "splotch_decimate_workspace_bytes", "splotch_decimate",
+           "splotch_probe_mask", "splotch_learned_workspace_bytes", "splotch_render_learned",
+           "splotch_stream_workspace_size", "splotch_render_stream")
 MAX_VIEWS = 1024
 
 
@@ -129,6 +137,14 @@ def _lib():
         L.splotch_render_static.argtypes = [C.POINTER(Particles), C.POINTER(CameraS),
                                             C.POINTER(Colourmap), C.POINTER(Params),
                                             C.POINTER(Image)]
+        L.splotch_stream_workspace_size.restype = C.c_int
+        L.splotch_stream_workspace_size.argtypes = [C.POINTER(Particles), C.c_int64, C.c_int64,
+                                                    C.POINTER(CameraS), C.POINTER(Params),
+                                                    C.POINTER(C.c_size_t)]
+        L.splotch_render_stream.restype = C.c_int
+        L.splotch_render_stream.argtypes = [C.POINTER(Particles), C.c_int64, C.c_int64,
+                                            C.POINTER(CameraS), C.POINTER(Colourmap),
+                                            C.POINTER(Params), C.POINTER(Image)]
         L.splotch_project.restype = C.c_int
         L.splotch_project.argtypes = [C.POINTER(Particles), C.POINTER(CameraS), C.POINTER(Params),
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -188,7 +204,8 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
                   tile=0, profile=False, seg_records=0, tile_mask=None,
-                  splat_variant=0, batch_streams=0, kernel=0, emission_is_source=0) -> Params:
+                  splat_variant=0, batch_streams=0, kernel=0, emission_is_source=0,
+                  split_pixels=0) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
@@ -202,13 +219,14 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.accumulate = 1 if accumulate else 0
     p.compensated = 1 if compensated else 0
     p.tile = int(tile)
-    p.profile = 1 if profile else 0
+    p.profile = int(profile)
     p.seg_records = int(seg_records)
     p.tile_mask = None if tile_mask is None else C.c_void_p(tile_mask.data_ptr())
     p.splat_variant = int(splat_variant)
     p.batch_streams = int(batch_streams)
     p.kernel = int(kernel)
     p.emission_is_source = int(emission_is_source)
+    p.split_pixels = int(split_pixels)
     return p
 
 
@@ -318,16 +336,17 @@ def _setup(parts, cam, species, max_pairs, workspace, **kw):
 def render(parts: dict, cam, palette, species, image=None, *, sigma_over_h=1.0, trunc_f=2.0,
            accumulate=False, compensated=False, tile=0, max_pairs=0, workspace=None,
            stats=False, profile=False, seg_records=0, tile_mask=None, splat_variant=0,
-           palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0):
+           palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0, split_pixels=0):
     """Render into image (planar float32 [3, H, W] device tensor; allocated
     if None).  Returns the image, or (image, stats dict) with stats=True
-    (profile=True adds per-stage milliseconds to the stats)."""
+    (profile=1 adds per-stage milliseconds to the stats, profile=2 also the
+    composited-contribution counts)."""
     import torch
     P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
                              trunc_f=trunc_f, accumulate=accumulate, compensated=compensated,
                              tile=tile, profile=profile, seg_records=seg_records,
                              tile_mask=tile_mask, splat_variant=splat_variant, kernel=kernel,
-                             emission_is_source=emission_is_source)
+                             emission_is_source=emission_is_source, split_pixels=split_pixels)
     stats = stats or profile
     if image is None:
         image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)
@@ -374,6 +393,60 @@ def render_static(parts: dict, cam, palette, species, image, *, sigma_over_h=1.0
     return (image, st.as_dict()) if stats else image
 
 
+def host_particles_struct(parts: dict) -> Particles:
+    """parts: dict of contiguous host (CPU) tensors with the fields of
+    particles_struct; pinned memory lets the copies overlap the work."""
+    import torch
+    for k, t in parts.items():
+        if t is not None and t.device.type != "cpu":
+            raise ValueError(f"host particle field {k} must be a CPU tensor")
+    P = Particles()
+    n = int(parts["x"].numel())
+    for k in ("x", "y", "z", "h", "value", "rho0", "value_g", "value_b"):
+        t = parts.get(k)
+        if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or
+                              t.numel() != n):
+            raise ValueError(f"particle field {k} must be contiguous float32 of length {n}")
+    P.n = n
+    P.x, P.y, P.z, P.h, P.value = (_ptr(parts[k]) for k in ("x", "y", "z", "h", "value"))
+    P.rho0 = _ptr(parts.get("rho0"))
+    P.species = _ptr(parts.get("species"))
+    P.value_g = _ptr(parts.get("value_g"))
+    P.value_b = _ptr(parts.get("value_b"))
+    return P
+
+
+def render_stream(host_parts: dict, cam, palette, species, image=None, *, subset=1 << 22,
+                  slab=1 << 24, device="cuda", stats=False, palette_absorb=None, **kw):
+    """splotch_render_stream: render a host-resident particle set (dict of
+    CPU tensors, ideally pinned) in subsets of `subset` particles and, with
+    ordered species, depth slabs of at most `slab` particles.  Returns the
+    image (or (image, stats))."""
+    import torch
+    P = host_particles_struct(host_parts)
+    cs = cam if isinstance(cam, CameraS) else camera_struct(cam)
+    prm = params_struct(species, **kw)
+    out = C.c_size_t(0)
+    _check(_lib().splotch_stream_workspace_size(C.byref(P), int(subset), int(slab), C.byref(cs),
+                                                C.byref(prm), C.byref(out)),
+           "splotch_stream_workspace_size")
+    ws = get_workspace(int(out.value), torch.device(device))
+    prm.workspace = C.c_void_p(ws.data_ptr())
+    prm.workspace_bytes = int(out.value)
+    prm.stream = _stream_ptr(torch.device(device))
+    if image is None:
+        image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=device)
+    cm = colourmap_struct(palette, palette_absorb)
+    img = Image(C.c_void_p(image.data_ptr()), cs.width, cs.height)
+    st = Stats()
+    if stats:
+        prm.stats = C.pointer(st)
+    _check(_lib().splotch_render_stream(C.byref(P), int(subset), int(slab), C.byref(cs),
+                                        C.byref(cm), C.byref(prm), C.byref(img)),
+           "splotch_render_stream")
+    return (image, st.as_dict()) if stats else image
+
+
 def project(parts: dict, cam, species, *, sigma_over_h=1.0, trunc_f=2.0, tile=0,
             workspace=None):
     """Per-particle stage outputs: dict of device tensors status (int8),
@@ -398,12 +471,12 @@ def project(parts: dict, cam, species, *, sigma_over_h=1.0, trunc_f=2.0, tile=0,
 
 
 def bin_pairs(parts: dict, cam, species, *, sigma_over_h=1.0, trunc_f=2.0, tile=0,
-              max_pairs=0, workspace=None):
+              max_pairs=0, workspace=None, split_pixels=0):
     """Per-tile particle lists: (tile_start, tile_end, pair_particle) device
     int32 tensors (uint32 bits) and the pair count."""
     import torch
     P, cs, prm, dev = _setup(parts, cam, species, max_pairs, workspace, sigma_over_h=sigma_over_h,
-                             trunc_f=trunc_f, tile=tile)
+                             trunc_f=trunc_f, tile=tile, split_pixels=split_pixels)
     T = tile or 16
     nt = ((cs.width + T - 1) // T) * ((cs.height + T - 1) // T)
     cap = max_pairs or (4 * P.n + 65536)
@@ -431,7 +504,8 @@ def _side_stream(device):
 def render_batch(parts: dict, cams, palette, species, images=None, *, graph=False,
                  sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False, tile=0,
                  max_pairs=0, seg_records=0, workspace=None, stats=False, splat_variant=0,
-                 streams=1, palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0):
+                 streams=1, palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0,
+                 split_pixels=0):
     """Render several camera views of one particle set (splotch_render_batch).
     images: list of [3, H_v, W_v] float32 device tensors (allocated if None).
     graph=True captures the batch into a HIP graph on first use and replays
@@ -450,7 +524,7 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
                         accumulate=accumulate, compensated=compensated, tile=tile,
                         seg_records=seg_records, splat_variant=splat_variant,
                         batch_streams=streams, kernel=kernel,
-                        emission_is_source=emission_is_source)
+                        emission_is_source=emission_is_source, split_pixels=split_pixels)
     T = tile or 16
     big = max(range(nv), key=lambda v: (-(-cs[v].width // T)) * (-(-cs[v].height // T)))
     if workspace is None:

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsplotch.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "bin.hip", "splat.hip", "nn.hip", "nn_api.hip", "render_static.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "bin.hip", "splat.hip", "nn.hip", "nn_api.hip", "unet.hip",
+           "learned.hip", "stream.hip", "render_static.hip"]
 ARCH = os.environ.get("SPLOTCH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

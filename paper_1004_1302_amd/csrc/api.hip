@@ -26,7 +26,7 @@ constexpr int kMaxLanes = 4;                     // batch views in flight at onc
 struct Layout {
     size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
     size_t tstart, tend, mcount, seg_len, nseg, nmulti, seg_off, part_off, seg_scan, item_tile;
-    size_t partial, flags;
+    size_t partial, flags, split, split_cnt;
     size_t pk0, pk1, pv0, pv1;
     uint64_t max_items, max_slots;
     size_t total;
@@ -70,6 +70,8 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
         L.val1 = take(N * 4);
     }
     L.off = take((N + 1) * 8);
+    L.split = take(N * 4);  // processing positions of split particles
+    L.split_cnt = take(4);
     L.scan = take(scan_u32_u64_scratch_bytes(N));
     L.radix = take(radix_scratch_bytes(std::max<size_t>(L.ordered ? N : 0, (size_t)cap)));
     L.counters = take(kCntN * 8);
@@ -160,6 +162,7 @@ splotch_status validate_params(const splotch_params *p) {
         return SPLOTCH_E_UNSUPPORTED;
     if (p->accumulate != 0 && p->accumulate != 1) return SPLOTCH_E_INVALID_ARG;
     if (p->seg_records < 0) return SPLOTCH_E_INVALID_ARG;
+    if (p->profile < 0 || p->profile > 2) return SPLOTCH_E_INVALID_ARG;
     if (p->splat_variant < 0 || p->splat_variant > 3) return SPLOTCH_E_INVALID_ARG;
     if (p->batch_streams < 0 || p->batch_streams > kMaxLanes) return SPLOTCH_E_INVALID_ARG;
     for (int s = 0; s < p->n_species; ++s) {
@@ -183,6 +186,10 @@ splotch_status validate_particles(const splotch_particles *P) {
     if (P->n > 0 && (!P->x || !P->y || !P->z || !P->h || !P->value)) return SPLOTCH_E_INVALID_ARG;
     return SPLOTCH_OK;
 }
+
+}  // namespace
+
+namespace splotch {
 
 CamDev cam_dev(const splotch_camera *c) {
     CamDev d;
@@ -224,6 +231,10 @@ SpeciesDev species_dev(const splotch_params *p) {
     }
     return s;
 }
+
+}  // namespace splotch
+
+namespace {
 
 splotch_status validate_colourmap(const splotch_colourmap *m) {
     if (!m || m->n_entries < 2 || !m->rgb) return SPLOTCH_E_INVALID_ARG;
@@ -289,6 +300,16 @@ struct Prof {
     }
 };
 
+// Split threshold in pixels of a footprint box (Section 3.2: particles
+// influencing more pixels than a threshold are split; about the mean of
+// the window's width and height works well): 0 = (W + H) / 2, negative =
+// no splitting.
+uint64_t split_threshold(const splotch_params *p, const splotch_camera *cam) {
+    if (p->split_pixels < 0) return 0;
+    if (p->split_pixels == 0) return (uint64_t)(cam->width + cam->height) / 2;
+    return (uint64_t)p->split_pixels;
+}
+
 // Public splat_variant -> walking strategy (0 = the default).
 int splat_variant_of(int v) {
     switch (v) {
@@ -302,6 +323,7 @@ struct Ctx {
     Layout L;
     char *ws;
     hipStream_t s;
+    uint64_t split = 0;  // split threshold in pixels, 0 = no splitting
     uint32_t seg_min = kSegMin;
     const uint8_t *tile_mask = nullptr;
     Prof prof;
@@ -430,6 +452,9 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, uint32_t idx_m
     e.ntx = c.L.ntx;
     e.pair_key = pk0;
     e.pair_val = pv0;
+    e.split_pixels = c.split;
+    e.split_list = c.split ? c.at<uint32_t>(c.L.split) : nullptr;
+    e.split_count = c.at<uint32_t>(c.L.split_cnt);
     TRY(launch_emit(e, c.s));
     TRY(const_cast<Prof &>(c.prof).mark(3));
     int bits = 0;
@@ -553,6 +578,7 @@ splotch_status prepare(const splotch_particles *P, const splotch_camera *cam,
     c->s = reinterpret_cast<hipStream_t>(p->stream);
     c->seg_min = p->seg_records > 0 ? (uint32_t)p->seg_records : kSegMin;
     c->tile_mask = p->tile_mask;
+    c->split = split_threshold(p, cam);
     if (c->prof.start(p->profile != 0 && p->stats != nullptr, c->s) != hipSuccess)
         return SPLOTCH_E_DEVICE;
     return SPLOTCH_OK;
@@ -650,6 +676,9 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         e.tile = c.L.tile;
         e.ntx = Lv.ntx;
         e.qshift = block_mask_shift(c.L.tile, Lv.n_tiles);
+        e.split_pixels = split_threshold(p, cam);
+        e.split_list = e.split_pixels ? c.at<uint32_t>(c.L.split) : nullptr;
+        e.split_count = c.at<uint32_t>(c.L.split_cnt);
         uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
         uint32_t *pv0 = c.at<uint32_t>(c.L.pv0), *pv1 = c.at<uint32_t>(c.L.pv1);
         e.pair_key = pk0;
@@ -859,8 +888,8 @@ splotch_status splotch_render(const splotch_particles *P, const splotch_camera *
     sa.max_items = c.L.max_items;
     sa.seg_len = c.at<uint32_t>(c.L.seg_len);
     sa.qshift = block_mask_shift(c.L.tile, c.L.n_tiles);
-    // member statistics only where they are reported (profiled stats)
-    sa.count = (p->stats != nullptr && p->profile != 0) ? 1 : 0;
+    // member statistics only where they are asked for (profile level 2)
+    sa.count = (p->stats != nullptr && p->profile >= 2) ? 1 : 0;
     TRY(launch_fill_u32(c.at<uint32_t>(c.L.mcount), 0u, (size_t)c.L.n_tiles * 4, c.s));
 
     const uint64_t total = plan.back();
@@ -983,6 +1012,7 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
         lanes[k].s = k == 0 ? c.s : ls->s[k - 1];
         lanes[k].seg_min = c.seg_min;
         lanes[k].tile_mask = c.tile_mask;
+        lanes[k].split = c.split;
     }
     if (!use_graph) {
         if ((st = enqueue_batch(lanes, ls, P, n_views, cams, cmap, p, images)) != SPLOTCH_OK)

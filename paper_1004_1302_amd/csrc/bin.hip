@@ -18,6 +18,30 @@ __global__ void k_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t 
         dst[k] = src[idx[k]];
 }
 
+// The pair key of tile (tx, ty) for a particle box [i0, i1] x [j0, j1]:
+// the tile index, and above it (qshift > 0) the mask of the tile's 8x8
+// blocks the box meets (a rectangle of them).
+__device__ __forceinline__ uint32_t pair_key(const EmitArgs &a, int tx, int ty, int i0, int i1,
+                                             int j0, int j1) {
+    const int T = a.tile, QW = T / 8;
+    uint32_t key = (uint32_t)(ty * a.ntx + tx);
+    if (a.qshift) {
+        const int qx0 = (max(i0, tx * T) - tx * T) >> 3, qx1 = (min(i1, tx * T + T - 1) - tx * T) >> 3;
+        const int qy0 = (max(j0, ty * T) - ty * T) >> 3, qy1 = (min(j1, ty * T + T - 1) - ty * T) >> 3;
+        const uint32_t row = ((2u << qx1) - 1u) & ~((1u << qx0) - 1u);
+        uint32_t m = 0;
+        for (int qy = qy0; qy <= qy1; ++qy) m |= row << (qy * QW);
+        key |= m << a.qshift;
+    }
+    return key;
+}
+
+// One thread per particle in processing order writes its pairs at its
+// offset, tile rows bottom to top, tiles left to right.  Particles whose
+// footprint box covers more than split_pixels pixels are split (Section
+// 3.2: a large particle's task divided into several over subsets of its
+// pixels): they are queued and their pairs written by a whole workgroup
+// in k_emit_split, into the same slots.
 __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     const uint64_t k = a.first + (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (k >= a.last) return;
@@ -26,6 +50,15 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     if (c == 0) return;
     const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
     const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
+    if (a.split_list) {
+        const uint64_t bw = ((bb.x >> kBboxBits) & kBboxMask) - (bb.x & kBboxMask) + 1;
+        const uint64_t bh = ((bb.y >> kBboxBits) & kBboxMask) - (bb.y & kBboxMask) + 1;
+        if (bw * bh > a.split_pixels) {
+            const uint32_t q = atomicAdd(a.split_count, 1u);
+            a.split_list[q] = (uint32_t)k;
+            return;
+        }
+    }
     const int T = a.tile;
     const int tx0 = (int)(bb.x & kBboxMask) / T, tx1 = (int)((bb.x >> kBboxBits) & kBboxMask) / T;
     const int ty0 = (int)(bb.y & kBboxMask) / T, ty1 = (int)((bb.y >> kBboxBits) & kBboxMask) / T;
@@ -36,25 +69,40 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     if (o + c > a.cap && a.overflow) *a.overflow = 1u;
     const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
     const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
-    const int QW = T / 8;
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
             if (a.tile_mask && !a.tile_mask[ty * a.ntx + tx]) continue;
             if (o >= a.cap) return;
-            uint32_t key = (uint32_t)(ty * a.ntx + tx);
-            if (a.qshift) {
-                // the tile's 8x8 blocks the box meets: a rectangle of them
-                const int qx0 = (max(i0, tx * T) - tx * T) >> 3, qx1 = (min(i1, tx * T + T - 1) - tx * T) >> 3;
-                const int qy0 = (max(j0, ty * T) - ty * T) >> 3, qy1 = (min(j1, ty * T + T - 1) - ty * T) >> 3;
-                const uint32_t row = ((2u << qx1) - 1u) & ~((1u << qx0) - 1u);
-                uint32_t m = 0;
-                for (int qy = qy0; qy <= qy1; ++qy) m |= row << (qy * QW);
-                key |= m << a.qshift;
-            }
-            a.pair_key[o] = key;
+            a.pair_key[o] = pair_key(a, tx, ty, i0, i1, j0, j1);
             a.pair_val[o] = i;
             ++o;
         }
+}
+
+// Split particles: workgroups take queued particles in turn and write
+// pair t of a particle (its t-th tile, in k_emit's order) at offset + t.
+// Only used without a tile mask, where pair t is tile t of the box.
+__global__ __launch_bounds__(kThreads) void k_emit_split(EmitArgs a) {
+    const uint32_t nq = *a.split_count;
+    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const uint64_t k = a.split_list[q];
+        const uint64_t o0 = a.off[k];
+        const uint32_t c = (uint32_t)(a.off[k + 1] - o0);
+        const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
+        const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
+        const int T = a.tile;
+        const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
+        const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
+        const int tx0 = i0 / T, ty0 = j0 / T, nx = i1 / T - tx0 + 1;
+        const uint64_t o = o0 - a.base;
+        if (o + c > a.cap && a.overflow && threadIdx.x == 0) *a.overflow = 1u;
+        for (uint32_t t = threadIdx.x; t < c; t += kThreads) {
+            if (o + t >= a.cap) break;
+            const int tx = tx0 + (int)(t % (uint32_t)nx), ty = ty0 + (int)(t / (uint32_t)nx);
+            a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1);
+            a.pair_val[o + t] = i;
+        }
+    }
 }
 
 // Boundaries of each tile's run in the sorted pair keys.  Each thread
@@ -149,8 +197,17 @@ hipError_t launch_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t 
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
     const uint64_t n = a.last - a.first;
     if (n == 0) return hipSuccess;
+    EmitArgs e = a;
+    if (e.tile_mask) e.split_list = nullptr;  // split only where pair t is tile t
+    if (e.split_list) {
+        hipError_t r = launch_fill_u32(e.split_count, 0u, 1, s);
+        if (r != hipSuccess) return r;
+    }
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, a);
+                       s, e);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess || !e.split_list) return r;
+    hipLaunchKernelGGL(k_emit_split, dim3(2048), dim3(kThreads), 0, s, e);
     return hipGetLastError();
 }
 

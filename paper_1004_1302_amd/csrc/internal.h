@@ -68,6 +68,18 @@ struct ProjectArgs {
     uint32_t *o_key;
 };
 
+}  // namespace splotch
+
+struct splotch_camera;
+struct splotch_params;
+
+namespace splotch {
+
+// Device views of the camera (promoted to binary64) and of the per-species
+// settings (api.hip).
+CamDev cam_dev(const splotch_camera *c);
+SpeciesDev species_dev(const splotch_params *p);
+
 // Workgroups are dealt to the 8 XCDs round-robin.  This maps workgroup b
 // of nblocks to the chunk it processes so that each XCD gets a contiguous
 // range of chunks: outputs of neighbouring chunks that share cache lines
@@ -135,6 +147,12 @@ struct EmitArgs {
     const uint8_t *tile_mask;  // per tile, 0 = skip; null = all tiles
     int qshift;                // > 0: key bit qshift + b set when the box meets 8x8 block b
     uint32_t *pair_key, *pair_val;
+    // split particles: boxes of more than split_pixels pixels are queued
+    // (split_list, capacity last - first; null = no splitting) and emitted
+    // by whole workgroups
+    uint64_t split_pixels;
+    uint32_t *split_list;    // processing positions (n < 2^32)
+    uint32_t *split_count;
 };
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
 // Bit of a pair key where the mask of the tile's 8x8 blocks that the

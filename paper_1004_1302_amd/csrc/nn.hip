@@ -448,10 +448,18 @@ __global__ void k_adam(float *w, bf16_t *w_bf, const float *g, float *m, float *
     }
 }
 
+// Tone-map scale: the host value, or the device sum times inv_count (the
+// image mean); a non-positive or non-finite scale becomes 1.
+__device__ __forceinline__ float tone_scale(const float *sum, float inv_count, float s) {
+    if (sum) s = sum[0] * inv_count;
+    return (s > 0.f && s < 3.0e38f) ? s : 1.f;
+}
+
 // Tone map of a planar float image [3][h][w] into NHWC with c channels
 // (channels >= 3 zero): out = log1p(img / s), s > 0 per image.
-__global__ void k_tonemap(const float *img, int h, int w, float s, int c, float *out_f,
-                          bf16_t *out_bf) {
+__global__ void k_tonemap(const float *img, int h, int w, const float *sum, float inv_count,
+                          float s0, int c, float *out_f, bf16_t *out_bf) {
+    const float s = tone_scale(sum, inv_count, s0);
     const size_t total = (size_t)h * w * c;
     const size_t plane = (size_t)h * w;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -466,7 +474,9 @@ __global__ void k_tonemap(const float *img, int h, int w, float s, int c, float 
 }
 
 // Inverse tone map from NHWC (first 3 channels) to planar [3][h][w].
-__global__ void k_untonemap(const float *in, int h, int w, float s, int c, float *img) {
+__global__ void k_untonemap(const float *in, int h, int w, const float *sum, float inv_count,
+                            float s0, int c, float *img) {
+    const float s = tone_scale(sum, inv_count, s0);
     const size_t plane = (size_t)h * w;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < 3 * plane;
          e += (size_t)gridDim.x * blockDim.x) {
@@ -628,15 +638,16 @@ hipError_t adam(float *w, bf16_t *w_bf, const float *g, float *m, float *v, size
 }
 
 hipError_t tonemap(const float *img, int h, int w, float scale, int c, float *out_f,
-                   bf16_t *out_bf, hipStream_t s) {
+                   bf16_t *out_bf, hipStream_t s, const float *sum, float inv_count) {
     hipLaunchKernelGGL(k_tonemap, dim3(grid_for((size_t)h * w * c)), dim3(256), 0, s, img, h, w,
-                       scale, c, out_f, out_bf);
+                       sum, inv_count, scale, c, out_f, out_bf);
     return hipGetLastError();
 }
 
-hipError_t untonemap(const float *in, int h, int w, float scale, int c, float *img, hipStream_t s) {
+hipError_t untonemap(const float *in, int h, int w, float scale, int c, float *img, hipStream_t s,
+                     const float *sum, float inv_count) {
     hipLaunchKernelGGL(k_untonemap, dim3(grid_for((size_t)h * w * 3)), dim3(256), 0, s, in, h, w,
-                       scale, c, img);
+                       sum, inv_count, scale, c, img);
     return hipGetLastError();
 }
 

@@ -39,9 +39,13 @@ hipError_t mse(const float *pred, const float *target, float *grad, size_t pixel
                int used, float *loss_part, int nblocks, hipStream_t s);
 hipError_t adam(float *w, bf16_t *w_bf, const float *g, float *m, float *v, size_t n, float lr,
                 float b1, float b2, float eps, int step, hipStream_t s);
+// Tone map with scale s: `scale`, or, when sum is not null, sum[0] *
+// inv_count read on the device (the image mean, no host read-back).
 hipError_t tonemap(const float *img, int h, int w, float scale, int c, float *out_f,
-                   bf16_t *out_bf, hipStream_t s);
-hipError_t untonemap(const float *in, int h, int w, float scale, int c, float *img, hipStream_t s);
+                   bf16_t *out_bf, hipStream_t s, const float *sum = nullptr,
+                   float inv_count = 0.f);
+hipError_t untonemap(const float *in, int h, int w, float scale, int c, float *img, hipStream_t s,
+                     const float *sum = nullptr, float inv_count = 0.f);
 hipError_t f2bf(const float *in, bf16_t *out, size_t n, hipStream_t s);
 
 }  // namespace nn

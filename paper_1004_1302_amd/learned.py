@@ -3,10 +3,12 @@ reconstruct the full render with a convolutional encoder-decoder; fall back
 to the full render when a cheap probe says the reconstruction is not good
 enough.
 
-Every arithmetic step runs in libsplotch's HIP kernels (the render, the
-BF16 matrix-core GEMM behind each 3x3 convolution, im2col, epilogues,
-pooling, upsampling, loss, Adam, tone mapping); torch only holds the
-buffers and the stream.
+Every step runs in libsplotch: the decimation, the renders, the network
+(splotch_nn: forward and backward passes, loss, Adam, checkpoints), the
+tone map with its scale found on the device, the probe and its PSNR, and
+the fallback decision (splotch_render_learned).  This module marshals
+arguments; torch holds the buffers and the stream.  `psnr_tonemapped` is a
+host helper for evaluating results, not part of the render path.
 
 Network: six levels with 32, 32, 64, 64, 128, 128 channels.  Each level has
 two 3x3 convolutions with ReLU; the encoder halves the resolution with 2x2
@@ -56,6 +58,23 @@ def _lib():
             "splotch_nn_tonemap": [P, I32, I32, F32, I32, P, P, P],
             "splotch_nn_untonemap": [P, I32, I32, F32, I32, P, P],
             "splotch_nn_f32_to_bf16": [P, P, I64, P],
+            "splotch_nn_param_bytes": [P, P],
+            "splotch_nn_create": [P, P, C.c_size_t, C.c_uint64, P, P],
+            "splotch_nn_destroy": [P],
+            "splotch_nn_workspace_bytes": [P, I32, I32, I32, P],
+            "splotch_nn_layer_info": [P, I32, I32, I32, I32, P],
+            "splotch_nn_forward": [P, P, P, I32, I32, I32, P, P, C.c_size_t, P],
+            "splotch_nn_loss_grad": [P, P, P, I32, I32, I32, P, P, P],
+            "splotch_nn_backward": [P, P, P, C.c_size_t, P],
+            "splotch_nn_adam_step": [P, F32, P],
+            "splotch_nn_save": [P, C.c_char_p, P],
+            "splotch_nn_load": [P, C.c_char_p, P],
+            "splotch_nn_reconstruct": [P, P, I32, I32, P, P, C.c_size_t, P],
+            "splotch_nn_train_step": [P, P, P, I32, I32, I32, F32, P, P, C.c_size_t, P],
+            "splotch_decimate": [P, I32, C.c_uint64, P, P, C.c_size_t, P],
+            "splotch_probe_mask": [I32, I32, I32, F32, C.c_uint64, P, P],
+            "splotch_learned_workspace_bytes": [P, I32, I32, I32, P],
+            "splotch_render_learned": [P, P, P, P, P, I32, P, P, C.c_size_t, P, F32, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -63,6 +82,11 @@ def _lib():
             fn.argtypes = args
         L.splotch_nn_gemm_splits.restype = C.c_int32
         L.splotch_nn_gemm_splits.argtypes = [C.c_int32, C.c_int32]
+        for name in ("splotch_nn_n_layers", "splotch_nn_get_step"):
+            getattr(L, name).restype = C.c_int32
+            getattr(L, name).argtypes = [P]
+        L.splotch_decimate_workspace_bytes.restype = C.c_size_t
+        L.splotch_decimate_workspace_bytes.argtypes = [I64]
         _declared = True
     return L
 
@@ -157,306 +181,196 @@ class Ops:
         _ok(self.L.splotch_nn_f32_to_bf16(_p(x), _p(out), n, _s()), "nn_f32_to_bf16")
 
 
-class Scratch:
-    """Named, grow-only device buffers."""
+class NNConfig(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("channels", C.c_int32 * 8), ("in_channels", C.c_int32)]
 
-    def __init__(self, device):
-        self.dev = device
-        self.bufs = {}
 
-    def get(self, name, numel, dtype):
+class NNLayer(C.Structure):
+    _fields_ = [("cin", C.c_int32), ("cout", C.c_int32), ("relu", C.c_int32), ("level", C.c_int32),
+                ("w", C.c_size_t), ("b", C.c_size_t), ("gw", C.c_size_t), ("gb", C.c_size_t),
+                ("w_bf16", C.c_size_t), ("x", C.c_size_t), ("y", C.c_size_t),
+                ("dy", C.c_size_t), ("dx", C.c_size_t)]
+
+
+NONE = (1 << 64) - 1  # SIZE_MAX: tensor not kept
+
+
+def _view(buf, off, numel, dtype):
+    """numel elements of dtype at byte offset off of a uint8 device tensor."""
+    import torch
+    size = torch.empty(0, dtype=dtype).element_size()
+    return buf[off:off + numel * size].view(dtype)
+
+
+class LayerView:
+    """Views of one convolution's parameters in the network's memory."""
+
+    def __init__(self, net, k, info):
         import torch
-        t = self.bufs.get(name)
-        if t is None or t.numel() < numel or t.dtype != dtype:
-            t = torch.empty(max(numel, 1), dtype=dtype, device=self.dev)
-            self.bufs[name] = t
-        return t[:numel]
-
-
-# ------------------------------------------------------------------ layers
-class Conv3x3:
-    """3x3 convolution, stride 1, zero padding.  Master weights in FP32 laid
-    out as the GEMM operand [9*cin][cout] (tap-major, then input channel),
-    with a BF16 copy and its [cout][9*cin] transpose for the fused forward
-    kernel; FP32 bias; Adam moments."""
-
-    def __init__(self, cin, cout, relu, rng, device, gain=1.0):
-        import torch
-        self.cin, self.cout, self.relu = cin, cout, relu
-        std = gain * math.sqrt(2.0 / (9 * cin))
-        w = rng.standard_normal((9 * cin, cout)) * std
-        self.w = torch.from_numpy(w.astype(np.float32)).to(device)
-        self.b = torch.zeros(cout, dtype=torch.float32, device=device)
-        self.w_bf = torch.empty((9 * cin, cout), dtype=torch.int16, device=device)
-        self.wt_bf = torch.empty((9 * cout, cin), dtype=torch.int16, device=device)
-        self.wf_bf = torch.empty((cout, 9 * cin), dtype=torch.int16, device=device)
-        self.gw = torch.empty_like(self.w)
-        self.gb = torch.empty_like(self.b)
-        self.mw = torch.zeros_like(self.w)
-        self.vw = torch.zeros_like(self.w)
-        self.mb = torch.zeros_like(self.b)
-        self.vb = torch.zeros_like(self.b)
-        self.ops = Ops()
-        self.refresh_bf16()
-
-    def refresh_bf16(self):
-        """BF16 copies of the master weights (after init, load or a step)."""
-        self.ops.f2bf(self.w, self.w_bf, self.w.numel())
-        self.ops.conv_weights(self.w_bf, self.wf_bf, self.cin, self.cout)
+        self.k, self.cin, self.cout, self.relu = k, info.cin, info.cout, info.relu
+        nw = 9 * self.cin * self.cout
+        pm = net.params
+        self.w = _view(pm, info.w, nw, torch.float32)
+        self.b = _view(pm, info.b, self.cout, torch.float32)
+        self.gw = _view(pm, info.gw, nw, torch.float32)
+        self.gb = _view(pm, info.gb, self.cout, torch.float32)
+        self.w_bf = _view(pm, info.w_bf16, nw, torch.int16)
 
     def n_params(self):
         return self.w.numel() + self.b.numel()
 
-    def forward(self, x_bf, n, h, w, out_bf, sc, tag, out_f=None, residual=None):
-        self.ops.conv3x3(x_bf, self.wf_bf, self.b, self.relu, residual, out_bf, out_f, n, h, w,
-                         self.cin, self.cout)
-
-    def backward(self, x_bf, y_bf, dy, n, h, w, sc, need_dx):
-        """dy: FP32 gradient of this layer's output.  Fills gw, gb and returns
-        the FP32 gradient of its input (or None)."""
-        P = n * h * w
-        dz_bf = sc.get("dz_bf", P * self.cout, self.w_bf.dtype)
-        dz_f = sc.get("dz_f", P * self.cout, self.w.dtype)
-        self.ops.relu_bwd(dy, y_bf, self.relu, dz_bf, dz_f, P * self.cout)
-        self.ops.colsum(dz_f, P, self.cout, self.gb,
-                        sc.get("colsum", 1024 * self.cout, self.w.dtype))
-        col = sc.get("col", P * 9 * self.cin, self.w_bf.dtype)
-        self.ops.im2col(x_bf, col, n, h, w, self.cin)
-        want = max(1, min(256, P // 2048))
-        splits = self.ops.splits(P, want)
-        cw = sc.get("gemm_w", splits * 9 * self.cin * self.cout, self.w.dtype)
-        self.ops.gemm(col, dz_bf, cw, 9 * self.cin, self.cout, P, 9 * self.cin, self.cout, 1, want)
-        self.ops.epilogue(cw, splits, 9 * self.cin, self.cout, None, 0, None, None, self.gw)
-        if not need_dx:
-            return None
-        self.ops.flip(self.w_bf, self.wt_bf, self.cout, self.cin)
-        colz = sc.get("colz", P * 9 * self.cout, self.w_bf.dtype)
-        self.ops.im2col(dz_bf, colz, n, h, w, self.cout)
-        dx = sc.get(f"dx_{id(self)}", P * self.cin, self.w.dtype)
-        self.ops.gemm(colz, self.wt_bf, dx, P, self.cin, 9 * self.cout, 9 * self.cout, self.cin,
-                      0, 1)
-        return dx
-
-    def adam(self, step, lr, b1=0.9, b2=0.999, eps=1e-8):
-        self.ops.adam(self.w, self.w_bf, self.gw, self.mw, self.vw, self.w.numel(), lr, b1, b2,
-                      eps, step)
-        self.ops.adam(self.b, None, self.gb, self.mb, self.vb, self.b.numel(), lr, b1, b2, eps,
-                      step)
-        self.ops.conv_weights(self.w_bf, self.wf_bf, self.cin, self.cout)
-
 
 class UNet:
-    """Six-level encoder-decoder on NHWC BF16 activations."""
+    """The library's reconstruction network (splotch_nn): weights in a
+    device buffer this object owns, activations in a workspace grown per
+    batch shape."""
 
-    def __init__(self, seed=0, device="cuda", levels=LEVELS):
-        rng = np.random.default_rng(seed)
-        self.levels = levels
-        self.dev = device
-        L = len(levels)
-        self.enc = []
-        for l in range(L):
-            cin = CIN if l == 0 else levels[l - 1]
-            self.enc.append((Conv3x3(cin, levels[l], True, rng, device),
-                             Conv3x3(levels[l], levels[l], True, rng, device)))
-        self.dec = [None] * (L - 1)
-        for l in range(L - 2, -1, -1):
-            cin = levels[l + 1] + levels[l]
-            self.dec[l] = (Conv3x3(cin, levels[l], True, rng, device),
-                           Conv3x3(levels[l], levels[l], True, rng, device))
-        self.out = Conv3x3(levels[0], CIN, False, rng, device, gain=0.1)
-        self.ops = Ops()
-        self.sc = Scratch(device)
-        self.step = 0
+    def __init__(self, seed=0, device="cuda", levels=LEVELS, cin=CIN):
+        import torch
+        self.L = _lib()
+        self.levels, self.cin, self.dev = tuple(levels), cin, device
+        cfg = NNConfig()
+        cfg.n_levels = len(levels)
+        for k, c in enumerate(levels):
+            cfg.channels[k] = int(c)
+        cfg.in_channels = cin
+        self.cfg = cfg
+        nb = C.c_size_t(0)
+        _ok(self.L.splotch_nn_param_bytes(C.byref(cfg), C.byref(nb)), "nn_param_bytes")
+        self.params = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _ok(self.L.splotch_nn_create(C.byref(cfg), _p(self.params), int(nb.value), int(seed),
+                                     _s(), C.byref(h)), "nn_create")
+        self.h = h
+        self.ws = None
+        self._layers = [LayerView(self, k, self.layer_info(k))
+                        for k in range(self.L.splotch_nn_n_layers(h))]
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.L.splotch_nn_destroy(h)
+            self.h = None
+
+    def layer_info(self, k, n=1, h=None, w=None):
+        m = 1 << (len(self.levels) - 1)
+        info = NNLayer()
+        _ok(self.L.splotch_nn_layer_info(self.h, k, n, h or m, w or m, C.byref(info)),
+            "nn_layer_info")
+        return info
 
     def layers(self):
         """Encoder levels top-down, decoder levels from the deepest up, then
         the output convolution (the order the FP64 reference uses)."""
-        out = [c for pair in self.enc for c in pair]
-        for l in range(len(self.levels) - 2, -1, -1):
-            out += list(self.dec[l])
-        return out + [self.out]
+        return self._layers
 
     def n_params(self):
-        return sum(c.n_params() for c in self.layers())
+        return sum(c.n_params() for c in self._layers)
 
-    def _act(self, name, numel):
-        import torch
-        return self.sc.get(name, numel, torch.int16)
+    @property
+    def step(self):
+        return int(self.L.splotch_nn_get_step(self.h))
 
-    def _f(self, name, numel):
+    def workspace(self, n, h, w):
         import torch
-        return self.sc.get(name, numel, torch.float32)
+        nb = C.c_size_t(0)
+        _ok(self.L.splotch_nn_workspace_bytes(self.h, n, h, w, C.byref(nb)), "nn_workspace_bytes")
+        if self.ws is None or self.ws.numel() < nb.value:
+            self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.dev)
+        return self.ws, int(nb.value)
+
+    def tensor(self, off, numel, dtype):
+        """A view of the workspace (activations and gradients of the last
+        pass, offsets from layer_info)."""
+        return _view(self.ws, off, numel, dtype)
 
     def forward(self, x_f, x_bf, n, h, w):
-        """x_f, x_bf: tone-mapped input [n*h*w, 32] (FP32 and BF16).  Returns
-        the FP32 output [n*h*w, 32] (first three channels meaningful)."""
-        L = len(self.levels)
-        self.shape = (n, h, w)
-        sizes = [(h >> l, w >> l) for l in range(L)]
-        self.saved = {}
-        inp = x_bf
-        for l in range(L):
-            hh, ww = sizes[l]
-            P = n * hh * ww
-            c = self.levels[l]
-            if l > 0:
-                pin = self._act(f"pool{l}", P * self.levels[l - 1])
-                self.ops.pool2(self.saved[f"e{l - 1}"], pin, n, 2 * hh, 2 * ww, self.levels[l - 1])
-                inp = pin
-            a = self._act(f"ea{l}", P * c)
-            e = self._act(f"e{l}", P * c)
-            self.enc[l][0].forward(inp, n, hh, ww, a, self.sc, f"enc{l}a")
-            self.enc[l][1].forward(a, n, hh, ww, e, self.sc, f"enc{l}b")
-            self.saved[f"ein{l}"] = inp
-            self.saved[f"ea{l}"] = a
-            self.saved[f"e{l}"] = e
-        d = self.saved[f"e{L - 1}"]
-        for l in range(L - 2, -1, -1):
-            hh, ww = sizes[l]
-            P = n * hh * ww
-            c = self.levels[l]
-            cat = self._act(f"cat{l}", P * (self.levels[l + 1] + c))
-            self.ops.up2_concat(d, self.levels[l + 1], self.saved[f"e{l}"], c, cat, n, hh, ww)
-            a = self._act(f"da{l}", P * c)
-            dd = self._act(f"d{l}", P * c)
-            self.dec[l][0].forward(cat, n, hh, ww, a, self.sc, f"dec{l}a")
-            self.dec[l][1].forward(a, n, hh, ww, dd, self.sc, f"dec{l}b")
-            self.saved[f"cat{l}"] = cat
-            self.saved[f"da{l}"] = a
-            self.saved[f"d{l}"] = dd
-            d = dd
-        P0 = n * h * w
-        y = self._f("y", P0 * CIN)
-        self.out.forward(d, n, h, w, None, self.sc, "out", out_f=y, residual=x_f)
-        self.saved["x_bf"] = x_bf
+        """x_f, x_bf: tone-mapped input [n*h*w, in_channels] (FP32 and BF16).
+        Returns the FP32 output of the same shape."""
+        import torch
+        ws, nb = self.workspace(n, h, w)
+        y = torch.empty(n * h * w * self.cin, dtype=torch.float32, device=self.dev)
+        _ok(self.L.splotch_nn_forward(self.h, _p(x_f), _p(x_bf), n, h, w, _p(y), _p(ws), nb,
+                                      _s()), "nn_forward")
         return y
 
+    def loss_grad(self, y, target, n, h, w):
+        import torch
+        g = torch.empty_like(y)
+        part = torch.empty(256, dtype=torch.float32, device=self.dev)
+        _ok(self.L.splotch_nn_loss_grad(self.h, _p(y), _p(target), n, h, w, _p(g), _p(part),
+                                        _s()), "nn_loss_grad")
+        return g, part
+
     def backward(self, gy):
-        """gy: FP32 gradient of the output [n*h*w, 32].  Fills every layer's
-        weight and bias gradients."""
-        n, h, w = self.shape
-        L = len(self.levels)
-        sizes = [(h >> l, w >> l) for l in range(L)]
-        ge = [None] * L
-        gd = self.out.backward(self.saved["d0"], None, gy, n, h, w, self.sc, True)
-        for l in range(L - 1):
-            hh, ww = sizes[l]
-            c = self.levels[l]
-            g = self.dec[l][1].backward(self.saved[f"da{l}"], self.saved[f"d{l}"], gd, n, hh, ww,
-                                        self.sc, True)
-            g = self.dec[l][0].backward(self.saved[f"cat{l}"], self.saved[f"da{l}"], g, n, hh, ww,
-                                        self.sc, True)
-            hl, wl = sizes[l + 1]
-            gd_next = self._f(f"gdn{l}", n * hl * wl * self.levels[l + 1])
-            ge[l] = self._f(f"ge{l}", n * hh * ww * c)
-            self.ops.up2_concat_bwd(g, self.levels[l + 1], c, gd_next, ge[l], n, hh, ww)
-            gd = gd_next
-        ge[L - 1] = gd
-        for l in range(L - 1, -1, -1):
-            hh, ww = sizes[l]
-            g = self.enc[l][1].backward(self.saved[f"ea{l}"], self.saved[f"e{l}"], ge[l], n, hh,
-                                        ww, self.sc, True)
-            g = self.enc[l][0].backward(self.saved[f"ein{l}"], self.saved[f"ea{l}"], g, n, hh, ww,
-                                        self.sc, l > 0)
-            if l > 0:
-                self.ops.pool2_bwd(g, ge[l - 1], n, 2 * hh, 2 * ww, self.levels[l - 1], True)
+        """gy: FP32 gradient of the last forward's output.  Fills every
+        layer's weight and bias gradients."""
+        _ok(self.L.splotch_nn_backward(self.h, _p(gy), _p(self.ws), self.ws.numel(), _s()),
+            "nn_backward")
 
     def adam_step(self, lr):
-        self.step += 1
-        for c in self.layers():
-            c.adam(self.step, lr)
+        _ok(self.L.splotch_nn_adam_step(self.h, float(lr), _s()), "nn_adam_step")
 
-    def state_dict(self):
-        d = {}
-        for k, c in enumerate(self.layers()):
-            d[f"w{k}"] = c.w.cpu().numpy()
-            d[f"b{k}"] = c.b.cpu().numpy()
-        return d
+    def save(self, path):
+        _ok(self.L.splotch_nn_save(self.h, str(path).encode(), _s()), "nn_save")
 
-    def load_state_dict(self, d):
-        import torch
-        for k, c in enumerate(self.layers()):
-            c.w.copy_(torch.from_numpy(d[f"w{k}"]))
-            c.b.copy_(torch.from_numpy(d[f"b{k}"]))
-            c.refresh_bf16()
+    def load(self, path):
+        _ok(self.L.splotch_nn_load(self.h, str(path).encode(), _s()), "nn_load")
 
 
-# ------------------------------------------------------------------ data
 def decimate(parts: dict, seed=7, keep=DECIMATE):
-    """Seeded 1/keep subset; smoothing lengths scaled by keep^(1/3) and the
-    density amplitude rho0 by keep^(1/3), so the expected emitted flux
-    (proportional to rho0 sigma^2 per particle) is preserved."""
+    """splotch_decimate: an exact seeded 1/keep subset (index order) with
+    smoothing lengths and density amplitudes scaled by keep^(1/3)."""
     import torch
+    L = _lib()
     n = int(parts["x"].numel())
-    g = torch.Generator(device="cpu")
-    g.manual_seed(seed)
-    m = max(1, n // keep)
-    idx = torch.randperm(n, generator=g)[:m].sort().values.to(parts["x"].device)
-    out = {k: t[idx].contiguous() for k, t in parts.items()}
-    k = float(keep) ** (1.0 / 3.0)
-    out["h"] = (out["h"] * k).contiguous()
-    r0 = out.get("rho0")
-    out["rho0"] = (r0 * k).contiguous() if r0 is not None else \
-        torch.full_like(out["x"], k)
+    m = max(1, n // keep) if n > 0 else 0
+    dev = parts["x"].device
+    out = {k: torch.empty(m, dtype=torch.float32, device=dev)
+           for k in ("x", "y", "z", "h", "value", "rho0")}
+    for k in ("value_g", "value_b"):
+        if parts.get(k) is not None:
+            out[k] = torch.empty(m, dtype=torch.float32, device=dev)
+    if parts.get("species") is not None:
+        out["species"] = torch.empty(m, dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(1, int(L.splotch_decimate_workspace_bytes(n))), dtype=torch.uint8,
+                     device=dev)
+    P_in = B.particles_struct(parts)
+    P_out = B.particles_struct(out)
+    _ok(L.splotch_decimate(C.byref(P_in), int(keep), int(seed), C.byref(P_out), _p(ws),
+                           ws.numel(), _s()), "decimate")
     return out
 
 
 class Reconstructor:
-    """Runs the network on a decimated render (and trains it)."""
+    """Image-level use of the network: training steps on render pairs and
+    reconstruction of a decimated render (all on the device)."""
 
     def __init__(self, net: UNet):
         self.net = net
-        self.ops = Ops()
-        self.sc = Scratch(net.dev)
-
-    def _scale(self, img):
-        import torch
-        part = self.sc.get("sum", 1, torch.float32)
-        self.ops.colsum(img.reshape(-1, 1), img.numel(), 1, part,
-                        self.sc.get("colsum", 1024, torch.float32))
-        s = float(part.item()) / img.numel()
-        return s if s > 0 else 1.0
-
-    def tonemap_pair(self, dec_imgs, full_imgs=None):
-        """Planar [3,H,W] images -> stacked NHWC tone maps (FP32 + BF16)."""
-        import torch
-        n = len(dec_imgs)
-        _, h, w = dec_imgs[0].shape
-        P = h * w
-        x_f = self.sc.get("x_f", n * P * CIN, torch.float32)
-        x_bf = self.sc.get("x_bf", n * P * CIN, torch.int16)
-        t_f = self.sc.get("t_f", n * P * CIN, torch.float32) if full_imgs is not None else None
-        scales = []
-        for k in range(n):
-            s = self._scale(dec_imgs[k])
-            scales.append(s)
-            self.ops.tonemap(dec_imgs[k], h, w, s, CIN, x_f[k * P * CIN:], x_bf[k * P * CIN:])
-            if full_imgs is not None:
-                self.ops.tonemap(full_imgs[k], h, w, s, CIN, t_f[k * P * CIN:], None)
-        return x_f, x_bf, t_f, scales
 
     def train_step(self, dec_imgs, full_imgs, lr=1e-3):
+        """One step on lists of planar [3,H,W] renders; returns the 256 loss
+        partials (device) of the step."""
         import torch
         n = len(dec_imgs)
         _, h, w = dec_imgs[0].shape
-        x_f, x_bf, t_f, _ = self.tonemap_pair(dec_imgs, full_imgs)
-        y = self.net.forward(x_f, x_bf, n, h, w)
-        P = n * h * w
-        gy = self.sc.get("gy", P * CIN, torch.float32)
-        part = self.sc.get("loss", 256, torch.float32)
-        self.ops.mse(y, t_f, gy, P, CIN, 3, part, 256)
-        self.net.backward(gy)
-        self.net.adam_step(lr)
+        ws, nb = self.net.workspace(n, h, w)
+        D = (C.c_void_p * n)(*[t.data_ptr() for t in dec_imgs])
+        Fi = (C.c_void_p * n)(*[t.data_ptr() for t in full_imgs])
+        part = torch.empty(256, dtype=torch.float32, device=self.net.dev)
+        _ok(self.net.L.splotch_nn_train_step(self.net.h, D, Fi, n, h, w, float(lr), _p(part),
+                                             _p(ws), nb, _s()), "nn_train_step")
         return part
 
     def infer(self, dec_img):
         """Reconstructed planar [3,H,W] image from one decimated render."""
         import torch
         _, h, w = dec_img.shape
-        x_f, x_bf, _, scales = self.tonemap_pair([dec_img])
-        y = self.net.forward(x_f, x_bf, 1, h, w)
+        ws, nb = self.net.workspace(1, h, w)
         out = torch.empty_like(dec_img)
-        self.ops.untonemap(y, h, w, scales[0], CIN, out)
+        _ok(self.net.L.splotch_nn_reconstruct(self.net.h, _p(dec_img), h, w, _p(out), _p(ws), nb,
+                                              _s()), "nn_reconstruct")
         return out
 
 
@@ -467,7 +381,8 @@ def psnr_tonemapped(img, ref):
     img = np.asarray(img, np.float64)
     s = ref.mean()
     if not s > 0:
-        return float("inf")
+        # a dark reference: agreement only if the image is dark too
+        return float("inf") if not img.max() > 0 else float("-inf")
     den = math.log1p(ref.max() / s)
     a = np.log1p(np.maximum(img, 0) / s) / den
     b = np.log1p(np.maximum(ref, 0) / s) / den
@@ -476,82 +391,63 @@ def psnr_tonemapped(img, ref):
 
 
 def probe_mask(width, height, tile, frac, seed, device):
-    """Seeded random set of screen tiles (uint8 mask), about frac of them."""
+    """splotch_probe_mask: a seeded sample of about frac of the screen tiles
+    (at least one), as a device uint8 mask and its host copy [nty, ntx]."""
     import torch
     ntx, nty = -(-width // tile), -(-height // tile)
-    rng = np.random.default_rng(seed)
-    m = (rng.uniform(size=ntx * nty) < frac).astype(np.uint8)
-    if not m.any():
-        m[rng.integers(0, m.size)] = 1
-    return torch.from_numpy(m).to(device), m.reshape(nty, ntx)
+    m = torch.empty(ntx * nty, dtype=torch.uint8, device=device)
+    _ok(_lib().splotch_probe_mask(width, height, tile, float(frac), int(seed), _p(m), _s()),
+        "probe_mask")
+    return m, m.cpu().numpy().reshape(nty, ntx)
 
 
 _probe_cache = {}
+_nn_ws = {}
 
 
-def _probe_sel(width, height, tile, frac, seed, device):
-    """probe_mask plus the flat indices of the probed pixels (device), cached
-    per setting so that a frame uploads nothing."""
-    import torch
-    key = (width, height, tile, frac, seed, str(device))
-    hit = _probe_cache.get(key)
-    if hit is None:
-        mask_t, mask = probe_mask(width, height, tile, frac, seed, device)
-        rows = np.repeat(np.repeat(mask, tile, 0), tile, 1)[:height, :width]
-        idx = torch.from_numpy(np.flatnonzero(rows)).to(device)
-        hit = (mask_t, mask, idx)
-        _probe_cache[key] = hit
-    return hit
-
-
-_side_streams = {}
-
-
-def _side_stream(device):
-    import torch
-    key = str(device)
-    if key not in _side_streams:
-        _side_streams[key] = torch.cuda.Stream(device=device)  # default priority
-    return _side_streams[key]
-
-
-def render_learned(parts_full, parts_dec, cam, palette, species, recon: Reconstructor, *,
+def render_learned(parts_full, parts_dec, cam, palette, species, recon, *,
                    threshold_db=40.0, probe_frac=0.02, seed=0, tile=16, dec_tile=32, **kw):
-    """Decimated render + reconstruction, checked by a probe: the full set
-    rendered on a seeded sample of tiles (of `tile` px).  Returns (image,
-    info) where info has the probe PSNR and whether the full render was used
-    instead.  The decimated render uses tiles of `dec_tile` px: its
-    footprints are 16^(1/3) times wider, and 32 px tiles render them fastest
-    (1.21 ms against 1.60 at 16 px for 1.25e6 particles at 1024²).
-
-    The probe renders on a side stream while the network runs: it waits
-    only for the decimated render (the two renders share the library's
-    workspace), and the caller's stream waits for it before the PSNR."""
+    """splotch_render_learned: decimated render, reconstruction, probe on a
+    seeded sample of tiles (rendered on a library stream while the network
+    runs), PSNR on the device, and the full render if the PSNR is below
+    threshold_db.  recon: a Reconstructor or UNet.  Returns (image, info)
+    with the probe PSNR and whether the full render was used."""
     import torch
-    main = torch.cuda.current_stream()
+    net = recon.net if isinstance(recon, Reconstructor) else recon
+    L = _lib()
     dev = parts_full["x"].device
-    mask_t, mask, idx = _probe_sel(cam.width, cam.height, tile, probe_frac, seed, dev)
-    # sized for the larger of the two renders, allocated on this stream
-    if kw.get("workspace") is None:
-        pk = {k: v for k, v in kw.items() if k in ("sigma_over_h", "trunc_f", "compensated",
-                                                   "accumulate", "seg_records", "splat_variant")}
-        mp = int(kw.get("max_pairs") or 0)
-        B.reserve_workspace(parts_full, cam, species, mp, tile=tile, tile_mask=mask_t, **pk)
-        B.reserve_workspace(parts_dec, cam, species, mp, tile=dec_tile, **pk)
-    dec = B.render(parts_dec, cam, palette, species, tile=dec_tile, **kw)
-    dec_done = main.record_event()
-    probe = torch.zeros_like(dec)
-    rec = recon.infer(dec)
-    side = _side_stream(dec.device)
-    side.wait_event(dec_done)
-    with torch.cuda.stream(side):
-        B.render(parts_full, cam, palette, species, probe, tile=tile, tile_mask=mask_t, **kw)
-    main.wait_stream(side)
-    probe.record_stream(side)
-    pair = torch.stack([rec.reshape(3, -1).index_select(1, idx),
-                        probe.reshape(3, -1).index_select(1, idx)]).cpu().numpy()
-    p = psnr_tonemapped(pair[0], pair[1])
-    info = dict(probe_psnr=p, fallback=bool(p < threshold_db), probe_tiles=int(mask.sum()))
-    if info["fallback"]:
-        return B.render(parts_full, cam, palette, species, tile=tile, **kw), info
-    return rec, info
+    key = (cam.width, cam.height, tile, probe_frac, seed, str(dev))
+    if key not in _probe_cache:
+        _probe_cache[key] = probe_mask(cam.width, cam.height, tile, probe_frac, seed, dev)
+    mask_t, mask = _probe_cache[key]
+    cs = cam if isinstance(cam, B.CameraS) else B.camera_struct(cam)
+    pk = {k: v for k, v in kw.items() if k in ("sigma_over_h", "trunc_f", "compensated",
+                                               "accumulate", "seg_records", "splat_variant",
+                                               "kernel", "emission_is_source")}
+    prm = B.params_struct(species, tile=tile, **pk)
+    mp = int(kw.get("max_pairs") or 0)
+    Pf, Pd = B.particles_struct(parts_full), B.particles_struct(parts_dec)
+    prm_d = B.params_struct(species, tile=dec_tile, **pk)
+    need = max(B.workspace_bytes(Pf.n, cs, prm, mp), B.workspace_bytes(Pd.n, cs, prm_d, mp))
+    ws = B.get_workspace(need, dev)
+    prm.workspace = C.c_void_p(ws.data_ptr())
+    prm.workspace_bytes = need
+    prm.stream = _s()
+    nb = C.c_size_t(0)
+    _ok(L.splotch_learned_workspace_bytes(net.h, cam.width, cam.height, tile, C.byref(nb)),
+        "learned_workspace_bytes")
+    lw = _nn_ws.get(str(dev))
+    if lw is None or lw.numel() < nb.value:
+        lw = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+        _nn_ws[str(dev)] = lw
+    image = torch.empty((3, cs.height, cs.width), dtype=torch.float32, device=dev)
+    cm = B.colourmap_struct(palette, kw.get("palette_absorb"))
+    img = B.Image(C.c_void_p(image.data_ptr()), cs.width, cs.height)
+    fb = C.c_int32(0)
+    ps = C.c_float(0)
+    _ok(L.splotch_render_learned(C.byref(Pf), C.byref(Pd), C.byref(cs), C.byref(cm),
+                                 C.byref(prm), int(dec_tile), net.h, _p(lw), int(nb.value),
+                                 _p(mask_t), float(threshold_db), C.byref(img), C.byref(fb),
+                                 C.byref(ps)), "render_learned")
+    info = dict(probe_psnr=float(ps.value), fallback=bool(fb.value), probe_tiles=int(mask.sum()))
+    return image, info

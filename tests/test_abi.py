@@ -267,3 +267,41 @@ def test_static_render_refuses_before_device_work():
                                      C.byref(img)) == 1
     assert "static scratch" in B.status_string(6)
 
+
+def test_network_and_learned_arguments_checked_on_host():
+    """Configuration and argument checks of the network object and the
+    learned path that need no device."""
+    from paper_1004_1302_amd import learned as LN
+    L = LN._lib()
+    cfg = LN.NNConfig()
+    cfg.n_levels = 6
+    for k, c in enumerate(LN.LEVELS):
+        cfg.channels[k] = c
+    cfg.in_channels = LN.CIN
+    nb = C.c_size_t(0)
+    assert L.splotch_nn_param_bytes(C.byref(cfg), C.byref(nb)) == 0
+    # per layer: FP32 weights, gradients and two moments, three BF16 copies
+    nw = 9 * 32 * 32 * 2 + 9 * 32 * 64 + 9 * 64 * 64 * 3 + 9 * 64 * 128 + 9 * 128 * 128 * 3 + \
+        9 * 96 * 32 + 9 * 128 * 64 + 9 * 192 * 64 + 9 * 256 * 128 + 9 * 32 * 32
+    assert nb.value >= nw * (4 * 4 + 2 * 3)
+    for bad in (dict(n_levels=0), dict(n_levels=9), dict(in_channels=16), dict(ch0=48)):
+        c2 = LN.NNConfig()
+        C.memmove(C.byref(c2), C.byref(cfg), C.sizeof(cfg))
+        if "n_levels" in bad:
+            c2.n_levels = bad["n_levels"]
+        if "in_channels" in bad:
+            c2.in_channels = bad["in_channels"]
+        if "ch0" in bad:
+            c2.channels[0] = bad["ch0"]
+        assert L.splotch_nn_param_bytes(C.byref(c2), C.byref(nb)) == 1
+    h = C.c_void_p()
+    assert L.splotch_nn_create(C.byref(cfg), None, 0, 1, None, C.byref(h)) == 2
+    assert L.splotch_decimate_workspace_bytes(1000) >= 8000
+    assert L.splotch_probe_mask(64, 64, 12, 0.1, 0, C.c_void_p(0x1000), None) == 1
+    assert L.splotch_probe_mask(64, 64, 16, 0.0, 0, C.c_void_p(0x1000), None) == 1
+    P = B.Particles()
+    P.n = 100
+    out = B.Particles()
+    out.n = 7  # must be 100 // 16 = 6
+    ws = C.c_void_p(0x1000)
+    assert L.splotch_decimate(C.byref(P), 16, 0, C.byref(out), ws, 1 << 20, None) == 1

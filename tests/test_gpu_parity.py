@@ -259,7 +259,7 @@ def test_statistics_do_not_change_the_image(torch_cuda):
     is the same bits either way."""
     scene = c2_small(60_000, seed=9, w=320, h=200)
     plain = gpu_render(scene, compensated=True)
-    counted, st = gpu_render(scene, compensated=True, profile=True)
+    counted, st = gpu_render(scene, compensated=True, profile=2)
     assert np.array_equal(plain, counted)
     assert st["n_member_pairs"] > 0 and 0 < st["n_member_absorbing"] < st["n_member_pairs"]
 
