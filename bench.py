@@ -488,7 +488,13 @@ def batch_leg(args, np, torch):
     ms_graph4 = timed(lambda: B.render_batch(parts, cams, pal, sp, images, graph=True, streams=4,
                                              **kw), reps)
     B.graph_cache_clear()
-    best = min(ms_graph, ms_batch4, ms_graph4, ms_batch)
+    # one persistent splat launch per group of four views
+    ms_pers4 = timed(lambda: B.render_batch(parts, cams, pal, sp, images, streams=4,
+                                            persistent=True, **kw), reps)
+    ms_pgraph4 = timed(lambda: B.render_batch(parts, cams, pal, sp, images, graph=True,
+                                              streams=4, persistent=True, **kw), reps)
+    B.graph_cache_clear()
+    best = min(ms_graph, ms_batch4, ms_graph4, ms_batch, ms_pers4, ms_pgraph4)
     out = {
         "metric": METRIC,
         "value": round(len(cams) / (best * 1e-3), 2),
@@ -505,6 +511,9 @@ def batch_leg(args, np, torch):
         "ms_per_batch_graph": round(ms_graph, 3),
         "ms_per_batch_eager_4_streams": round(ms_batch4, 3),
         "ms_per_batch_graph_4_streams": round(ms_graph4, 3),
+        "ms_per_batch_persistent_4_streams": round(ms_pers4, 3),
+        "ms_per_batch_persistent_graph_4_streams": round(ms_pgraph4, 3),
+        "speedup_best_vs_single_calls": round(ms_single / best, 3),
         "mparticle_views_per_s": round(n * len(cams) / (best * 1e-3) / 1e6, 1),
         "autotune_table": tuned["table"],
     }

@@ -179,7 +179,8 @@ typedef struct splotch_params {
     int32_t accumulate; /* 0: image = render; 1: composite over the image (it is
                            the light entering from behind every particle) */
     int32_t compensated; /* 1: compensated (Kahan) summation of emission */
-    int32_t tile;        /* tile edge in pixels: 0 (= 16), 8, 16 or 32 */
+    int32_t tile;        /* tile edge in pixels: 0 (= 16), 8, 16, 32 or 64 (64 with
+                            the row walk only, splat_variant 0 or 1) */
     int32_t profile;     /* 1: time each stage (needs stats); 2: also count the
                             composited contributions; other values:
                             SPLOTCH_E_INVALID_ARG */
@@ -231,6 +232,15 @@ typedef struct splotch_params {
                             never.  Speed only: the pairs and the image are
                             the same bits either way (not used with a
                             tile_mask). */
+    int32_t batch_persistent; /* splotch_render_batch only: 1 = views are
+                            prepared in groups of batch_streams (one per
+                            stream, projection to tile lists) and each group
+                            is splatted by one persistent launch whose
+                            workgroups take (view, tile segment, 8x8 block)
+                            units until none is left; needs the row walk
+                            (splat_variant 0 or 1, else
+                            SPLOTCH_E_UNSUPPORTED).  Images are the same
+                            bits as with 0. */
 } splotch_params;
 
 /* Output image: planar float32 [3][height][width], device. */

@@ -1,4 +1,4 @@
-"""Autotuner for the render's launch shape: tile edge (8, 16, 32 px) and the
+"""Autotuner for the render's launch shape: tile edge (8, 16, 32, 64 px) and the
 least records per tile-list segment (one workgroup each).
 
 Both knobs change only speed, never the image's integer decisions (pixel
@@ -16,7 +16,7 @@ import os
 
 from . import binding as B
 
-DEFAULT_TILES = (8, 16, 32)
+DEFAULT_TILES = (8, 16, 32, 64)
 DEFAULT_SEGS = (256, 1024, 4096)
 
 

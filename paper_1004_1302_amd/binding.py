@@ -86,7 +86,7 @@ class Params(C.Structure):
                 ("stream", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("stats", C.POINTER(Stats)),
                 ("kernel", C.c_int32), ("emission_is_source", C.c_int32),
-                ("split_pixels", C.c_int32)]
+                ("split_pixels", C.c_int32), ("batch_persistent", C.c_int32)]
 
 
 class Image(C.Structure):
@@ -205,7 +205,7 @@ def camera_look_at(eye, at, up, projection, fov_or_scale, width, height, z_near,
 def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False,
                   tile=0, profile=False, seg_records=0, tile_mask=None,
                   splat_variant=0, batch_streams=0, kernel=0, emission_is_source=0,
-                  split_pixels=0) -> Params:
+                  split_pixels=0, batch_persistent=0) -> Params:
     p = Params()
     if not 1 <= len(species) <= MAX_SPECIES:
         raise ValueError("1..8 species")
@@ -227,6 +227,7 @@ def params_struct(species, sigma_over_h=1.0, trunc_f=2.0, accumulate=False, comp
     p.kernel = int(kernel)
     p.emission_is_source = int(emission_is_source)
     p.split_pixels = int(split_pixels)
+    p.batch_persistent = int(batch_persistent)
     return p
 
 
@@ -505,7 +506,7 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
                  sigma_over_h=1.0, trunc_f=2.0, accumulate=False, compensated=False, tile=0,
                  max_pairs=0, seg_records=0, workspace=None, stats=False, splat_variant=0,
                  streams=1, palette_absorb=None, kernel=KERNEL_GAUSS2D, emission_is_source=0,
-                 split_pixels=0):
+                 split_pixels=0, persistent=False):
     """Render several camera views of one particle set (splotch_render_batch).
     images: list of [3, H_v, W_v] float32 device tensors (allocated if None).
     graph=True captures the batch into a HIP graph on first use and replays
@@ -524,7 +525,8 @@ def render_batch(parts: dict, cams, palette, species, images=None, *, graph=Fals
                         accumulate=accumulate, compensated=compensated, tile=tile,
                         seg_records=seg_records, splat_variant=splat_variant,
                         batch_streams=streams, kernel=kernel,
-                        emission_is_source=emission_is_source, split_pixels=split_pixels)
+                        emission_is_source=emission_is_source, split_pixels=split_pixels,
+                        batch_persistent=1 if persistent else 0)
     T = tile or 16
     big = max(range(nv), key=lambda v: (-(-cs[v].width // T)) * (-(-cs[v].height // T)))
     if workspace is None:

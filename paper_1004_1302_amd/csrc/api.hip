@@ -22,11 +22,12 @@ constexpr uint32_t kMaxChunks = 4096;
 constexpr uint64_t kMaxPairCap = 0xFFFF0000ull;  // pair indices are 32-bit
 constexpr uint32_t kSegMin = 1024;               // least records per list segment
 constexpr int kMaxLanes = 4;                     // batch views in flight at once
+static_assert(kMaxLanes <= kMaxGroup, "a persistent group holds one view per lane");
 
 struct Layout {
     size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
     size_t tstart, tend, mcount, seg_len, nseg, nmulti, seg_off, part_off, seg_scan, item_tile;
-    size_t partial, flags, split, split_cnt;
+    size_t partial, flags, sargs, split, split_cnt;
     size_t pk0, pk1, pv0, pv1;
     uint64_t max_items, max_slots;
     size_t total;
@@ -89,6 +90,7 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
     L.max_slots = std::min<uint64_t>(2 * kSegTarget, 2 * (cap / seg_min) + 2);
     L.seg_len = take(4);
     L.flags = take((size_t)SPLOTCH_MAX_VIEWS * 12);  // per view: overflow flag (u32), pairs (u64)
+    L.sargs = take(kMaxGroup * sizeof(SplatArgs));    // splat settings of a persistent group
     L.nseg = take((size_t)L.n_tiles * 4);
     L.nmulti = take((size_t)L.n_tiles * 4);
     L.seg_off = take(((size_t)L.n_tiles + 1) * 8);
@@ -158,13 +160,21 @@ splotch_status validate_params(const splotch_params *p) {
     if (p->n_species < 1 || p->n_species > SPLOTCH_MAX_SPECIES) return SPLOTCH_E_INVALID_ARG;
     if (!(p->sigma_over_h > 0.0f) || !isfinite(p->sigma_over_h)) return SPLOTCH_E_INVALID_ARG;
     if (!(p->trunc_f > 0.0f) || !isfinite(p->trunc_f)) return SPLOTCH_E_INVALID_ARG;
-    if (p->tile != 0 && p->tile != 8 && p->tile != 16 && p->tile != 32)
+    if (p->tile != 0 && p->tile != 8 && p->tile != 16 && p->tile != 32 && p->tile != 64)
+        return SPLOTCH_E_UNSUPPORTED;
+    // 64 px tiles only with the row walk (the other strategies hold a whole
+    // tile in one workgroup)
+    if (p->tile == 64 && p->splat_variant != 0 && p->splat_variant != 1)
         return SPLOTCH_E_UNSUPPORTED;
     if (p->accumulate != 0 && p->accumulate != 1) return SPLOTCH_E_INVALID_ARG;
     if (p->seg_records < 0) return SPLOTCH_E_INVALID_ARG;
     if (p->profile < 0 || p->profile > 2) return SPLOTCH_E_INVALID_ARG;
     if (p->splat_variant < 0 || p->splat_variant > 3) return SPLOTCH_E_INVALID_ARG;
     if (p->batch_streams < 0 || p->batch_streams > kMaxLanes) return SPLOTCH_E_INVALID_ARG;
+    if (p->batch_persistent != 0 && p->batch_persistent != 1) return SPLOTCH_E_INVALID_ARG;
+    // the persistent batch splat is a row walk
+    if (p->batch_persistent && p->splat_variant != 0 && p->splat_variant != 1)
+        return SPLOTCH_E_UNSUPPORTED;
     for (int s = 0; s < p->n_species; ++s) {
         const splotch_species &q = p->species[s];
         if (q.mode != SPLOTCH_ADDITIVE && q.mode != SPLOTCH_ORDERED) return SPLOTCH_E_INVALID_ARG;
@@ -255,6 +265,16 @@ void splat_colour_args(SplatArgs *sa, const splotch_particles *P, const splotch_
     sa->kernel3d = p->kernel == SPLOTCH_KERNEL_TRUNC3D ? 1 : 0;
     sa->source = p->emission_is_source ? 1 : 0;
     sa->sp = species_dev(p);
+    // E = A for every record of an ordered species with equal brightness
+    // and absorption, one colour table and E read as emission (Section 2's
+    // recommended setting); anything else may give E != A
+    sa->general = 0;
+    for (int s = 0; s < p->n_species; ++s) {
+        const splotch_species &q = p->species[s];
+        if (q.mode != SPLOTCH_ORDERED || q.absorption == 0.0f) continue;
+        if (q.brightness != q.absorption || m->rgb_absorb || p->emission_is_source)
+            sa->general = 1;
+    }
 }
 
 #define TRY(expr)                                      \
@@ -635,10 +655,12 @@ splotch_status lane_set(LaneSet **out) {
 
 // Queue view v on lane c (its workspace part and stream).  flags/totals
 // (per view) live in the first lane's workspace part.
+// With defer (persistent batches) the splat is not launched: its settings
+// are returned in *defer for the group launch.
 splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals,
                             const splotch_particles *P, const splotch_camera *cam,
                             const splotch_colourmap *cmap, const splotch_params *p,
-                            splotch_image *image) {
+                            splotch_image *image, SplatArgs *defer = nullptr) {
     const int64_t n = P->n;
     const uint64_t cap = c.L.pair_cap;
     const uint32_t nt = (uint32_t)(c.L.tile * c.L.tile);
@@ -730,6 +752,10 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         sa.compensated = p->compensated ? 1 : 0;
         sa.ordered = c.L.ordered ? 1 : 0;
         sa.variant = splat_variant_of(p->splat_variant);
+        if (defer) {
+            *defer = sa;
+            return SPLOTCH_OK;
+        }
         const uint32_t q = 64;
         const uint32_t grid = (uint32_t)((Lv.n_tiles + kSegTarget + q - 1) / q * q);
         TRY(launch_splat(sa, grid, c.s));
@@ -749,6 +775,36 @@ splotch_status enqueue_batch(std::vector<Ctx> &lanes, const LaneSet *ls,
     uint32_t *flags = c0.at<uint32_t>(c0.L.flags);
     uint64_t *totals = reinterpret_cast<uint64_t *>(flags + SPLOTCH_MAX_VIEWS);
     TRY(launch_fill_u32(flags, 0u, (size_t)nv, c0.s));
+    if (p->batch_persistent) {
+        // groups of K views: each lane prepares one view (projection to
+        // segments), then one persistent splat over the group on the
+        // caller's stream, then the views' merges; the next group's lanes
+        // start after them (they reuse the workspace parts)
+        SplatArgs *views = c0.at<SplatArgs>(c0.L.sargs);
+        for (int32_t g0 = 0; g0 < nv; g0 += K) {
+            const int G = std::min<int>(K, nv - g0);
+            if (G > 1) {
+                TRY(hipEventRecord(ls->fork, c0.s));
+                for (int k = 1; k < G; ++k) TRY(hipStreamWaitEvent(lanes[k].s, ls->fork, 0));
+            }
+            SplatArgs sa[kMaxGroup];
+            for (int k = 0; k < G; ++k) {
+                splotch_status st = enqueue_view(lanes[k], g0 + k, flags, totals, P, &cams[g0 + k],
+                                                 cmap, p, &images[g0 + k], &sa[k]);
+                if (st != SPLOTCH_OK) return st;
+                TRY(store_splat_args(sa[k], views + k, lanes[k].s));
+            }
+            if (G > 1) {
+                for (int k = 1; k < G; ++k) {
+                    TRY(hipEventRecord(ls->join[k - 1], lanes[k].s));
+                    TRY(hipStreamWaitEvent(c0.s, ls->join[k - 1], 0));
+                }
+            }
+            TRY(launch_splat_multi(views, G, sa[0], c0.s));
+            for (int k = 0; k < G; ++k) TRY(launch_merge(sa[k], c0.s));
+        }
+        return SPLOTCH_OK;
+    }
     if (K > 1) {
         TRY(hipEventRecord(ls->fork, c0.s));
         for (int k = 1; k < K; ++k) TRY(hipStreamWaitEvent(lanes[k].s, ls->fork, 0));

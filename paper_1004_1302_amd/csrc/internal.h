@@ -198,6 +198,7 @@ struct SplatArgs {
     int n_pal_abs;
     const float *value_g, *value_b;  // vector components 2 and 3 (vector species)
     int kernel3d;                // 1: column of the density cut to the f sigma ball
+    int general;                 // 1: some ordered species may have E != A
     int source;                  // 1: emission of ordered species is a source function
     SpeciesDev sp;
     float *image;
@@ -233,6 +234,16 @@ hipError_t launch_segments(const uint32_t *tile_start, const uint32_t *tile_end,
 // Grid size (upper bound on items) for a pass with npairs pairs.
 uint32_t splat_grid(uint32_t n_tiles, uint64_t npairs, uint32_t seg_len);
 hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s);
+// Persistent multi-view splat (row walk): views (device array of nv <=
+// kMaxGroup SplatArgs, written by store_splat_args) share one launch; like
+// holds the settings that pick the kernel (tile, ordering, compensation,
+// counting, column kernel) and must match every view's.  The views' merge
+// kernels follow separately (launch_merge).
+constexpr int kMaxGroup = 4;
+hipError_t store_splat_args(const SplatArgs &a, SplatArgs *dst, hipStream_t s);
+hipError_t launch_splat_multi(const SplatArgs *views, int nv, const SplatArgs &like,
+                              hipStream_t s);
+hipError_t launch_merge(const SplatArgs &a, hipStream_t s);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

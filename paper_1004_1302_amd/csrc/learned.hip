@@ -347,7 +347,7 @@ splotch_status splotch_decimate(const splotch_particles *in, int32_t keep, uint6
 splotch_status splotch_probe_mask(int32_t width, int32_t height, int32_t tile, float frac,
                                   uint64_t seed, uint8_t *mask, void *stream) {
     if (width <= 0 || height <= 0 || width > SPLOTCH_MAX_DIM || height > SPLOTCH_MAX_DIM ||
-        (tile != 8 && tile != 16 && tile != 32) || !(frac > 0.f) || !(frac <= 1.f) || !mask)
+        (tile != 8 && tile != 16 && tile != 32 && tile != 64) || !(frac > 0.f) || !(frac <= 1.f) || !mask)
         return SPLOTCH_E_INVALID_ARG;
     const uint32_t nt = (uint32_t)((width + tile - 1) / tile) * (uint32_t)((height + tile - 1) / tile);
     hipLaunchKernelGGL(k_probe_mask, dim3(1), dim3(1024), 0, st(stream), nt, seed, (double)frac,
@@ -361,7 +361,7 @@ splotch_status splotch_learned_workspace_bytes(splotch_nn *net, int32_t width, i
     size_t nn = 0;
     splotch_status r = splotch_nn_workspace_bytes(net, 1, height, width, &nn);
     if (r != SPLOTCH_OK) return r;
-    if (!bytes || (tile != 8 && tile != 16 && tile != 32)) return SPLOTCH_E_INVALID_ARG;
+    if (!bytes || (tile != 8 && tile != 16 && tile != 32 && tile != 64)) return SPLOTCH_E_INVALID_ARG;
     const uint32_t nt = (uint32_t)((width + tile - 1) / tile) * (uint32_t)((height + tile - 1) / tile);
     *bytes = learned_layout(nn, width, height, nt).total;
     return SPLOTCH_OK;
@@ -377,12 +377,12 @@ splotch_status splotch_render_learned(const splotch_particles *full,
     if (!full || !dec || !cam || !params || !net || !probe_mask || !image || !image->rgb ||
         !used_fallback || !probe_psnr || params->tile_mask || isnan(psnr_threshold))
         return SPLOTCH_E_INVALID_ARG;
-    if (dec_tile != 0 && dec_tile != 8 && dec_tile != 16 && dec_tile != 32)
+    if (dec_tile != 0 && dec_tile != 8 && dec_tile != 16 && dec_tile != 32 && dec_tile != 64)
         return SPLOTCH_E_UNSUPPORTED;
     if (image->width != cam->width || image->height != cam->height) return SPLOTCH_E_INVALID_ARG;
     const int W = cam->width, H = cam->height;
     const int T = params->tile == 0 ? 16 : params->tile;
-    if (T != 8 && T != 16 && T != 32) return SPLOTCH_E_UNSUPPORTED;
+    if (T != 8 && T != 16 && T != 32 && T != 64) return SPLOTCH_E_UNSUPPORTED;
     const int ntx = (W + T - 1) / T, nty = (H + T - 1) / T;
     const uint32_t n_tiles = (uint32_t)(ntx * nty);
     size_t nn_bytes = 0;

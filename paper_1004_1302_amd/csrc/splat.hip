@@ -75,42 +75,152 @@ __device__ __forceinline__ void add_term(float &C, float &K, float T, float v) {
         C = ORDERED ? __builtin_fmaf(T, v, C) : C + v;
 }
 
-// One member contribution: weight w = exp(-q^2) of the particle at this
-// pixel, emission e = E c rho0 and absorption x = A c rho0 per channel.
-// Emission-only particles (A = 0) add w e (times the transmittance when
-// ordered); absorbing ones apply the exact per-particle solution of Eq. (1).
-template <bool ORDERED, bool KAHAN>
-__device__ __forceinline__ void composite(bool emit_only, float w, float e0, float e1, float e2,
-                                          float a0, float a1, float a2, float &C0, float &C1,
-                                          float &C2, float &K0, float &K1, float &K2, float &T0,
-                                          float &T1, float &T2) {
+// Kinds of record (uniform per record): emission only (A = 0), E = A per
+// channel, and any other absorber.
+enum : int { kKindEmit = 0, kKindEqual = 1, kKindGeneral = 2 };
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// The column a member pixel's ray sees, per unit rho0, as 2^-q g: the
+// Gaussian exp(-d^2/sigma_s^2) = 2^-q with q = d2 log2(e)/sigma_s^2, and
+// g = erf(sqrt(f^2 - d^2/sigma_s^2)) when the density is cut to the f sigma
+// ball (f^2 - d^2/sigma_s^2 = (r2 - d2)/sigma_s^2), else 1.
+struct Col {
+    float q, g;
+};
+
+template <bool K3D>
+__device__ __forceinline__ Col column(float d2, float r2, float qs) {
 #pragma clang fp contract(off)
-    e0 *= w;
-    e1 *= w;
-    e2 *= w;
-    if (!ORDERED || emit_only) {
-        add_term<ORDERED, KAHAN>(C0, K0, T0, e0);
-        add_term<ORDERED, KAHAN>(C1, K1, T1, e1);
-        add_term<ORDERED, KAHAN>(C2, K2, T2, e2);
+    Col c;
+    c.q = d2 * qs;
+    c.g = 1.0f;
+    if (K3D) {
+        const float rem = fmaxf(r2 - d2, 0.0f) * (qs * 0.6931471805599453f);
+        c.g = erff(sqrtf(rem));
+    }
+    return c;
+}
+
+// Per-pixel state: colour C with its compensation K; for ordered sets the
+// optical depth L crossed so far per channel (the transmittance is
+// exp(-L)) and, when the set has absorbers with E != A (GEN), the
+// transmittance D those absorbers removed and whether an E = A absorber
+// covered the pixel.
+struct Px {
+    float C0, C1, C2, K0, K1, K2, L0, L1, L2, D0, D1, D2, seen;
+};
+
+__device__ __forceinline__ void px_init(Px &p) {
+    p.C0 = p.C1 = p.C2 = 0.f;
+    p.K0 = p.K1 = p.K2 = 0.f;
+    p.L0 = p.L1 = p.L2 = 0.f;
+    p.D0 = p.D1 = p.D2 = 0.f;
+    p.seen = 0.f;
+}
+
+// exp(-x) and phi(x) for three channels: the series almost always; the rare
+// large optical depth redoes its channels (one branch, skipped when no lane
+// needs it).
+__device__ __forceinline__ void ex_phi3(float x0, float x1, float x2, float &ex0, float &ex1,
+                                        float &ex2, float &ph0, float &ph1, float &ph2) {
+    ex_phi_small(x0, ex0, ph0);
+    ex_phi_small(x1, ex1, ph1);
+    ex_phi_small(x2, ex2, ph2);
+    if (fmaxf(x0, fmaxf(x1, x2)) >= kSeriesMax) {
+        ex_phi(x0, ex0, ph0);
+        ex_phi(x1, ex1, ph1);
+        ex_phi(x2, ex2, ph2);
+    }
+}
+
+// Transmittance exp(-L) of one channel times the column 2^-q g.
+__device__ __forceinline__ float trans_col(float L, Col c) {
+    return __builtin_amdgcn_exp2f(-__builtin_fmaf(L, kLog2e, c.q)) * c.g;
+}
+
+// One member contribution of a particle with emission e = E c rho0 and
+// absorption a = A c rho0 per channel and column c at this pixel: the exact
+// per-particle solution of Eq. (1), front to back, with T = exp(-L):
+//   Emission only (A = 0): C += T e w.
+//   E = A: I <- I e^{-x} + (1 - e^{-x}) with x = a w, so the particle adds
+//     exactly the transmittance it removes, T (1 - e^{-x}).  Only the
+//     optical depth is carried (L += x); the sum of those additions,
+//     (1 - exp(-L)) less what other absorbers removed (D), is added once at
+//     the end (finish).  Carrying L rather than a product of factors keeps
+//     faint pixels exact to rounding: 1 - exp(-L) = -expm1(-L).
+//   Other absorbers: C += T e w phi(x), D += T x phi(x), L += x.
+// Additive (unordered) sets: C += e w.
+template <bool ORDERED, bool KAHAN, bool GEN>
+__device__ __forceinline__ void composite(int kind, Col c, float e0, float e1, float e2, float a0,
+                                          float a1, float a2, Px &p) {
+#pragma clang fp contract(off)
+    if (!ORDERED) {
+        const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
+        add_term<false, KAHAN>(p.C0, p.K0, 1.f, e0 * w);
+        add_term<false, KAHAN>(p.C1, p.K1, 1.f, e1 * w);
+        add_term<false, KAHAN>(p.C2, p.K2, 1.f, e2 * w);
+    } else if (kind == kKindEmit) {
+        add_term<false, KAHAN>(p.C0, p.K0, 1.f, e0 * trans_col(p.L0, c));
+        add_term<false, KAHAN>(p.C1, p.K1, 1.f, e1 * trans_col(p.L1, c));
+        add_term<false, KAHAN>(p.C2, p.K2, 1.f, e2 * trans_col(p.L2, c));
+    } else if (kind == kKindEqual) {
+        const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
+        p.L0 += e0 * w;
+        p.L1 += e1 * w;
+        p.L2 += e2 * w;
+        if (GEN) p.seen = 1.f;
     } else {
+        const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
         const float x0 = a0 * w, x1 = a1 * w, x2 = a2 * w;
-        // the series almost always; the rare large optical depth redoes its
-        // channels (one branch, skipped when no lane needs it)
         float ex0, ex1, ex2, ph0, ph1, ph2;
-        ex_phi_small(x0, ex0, ph0);
-        ex_phi_small(x1, ex1, ph1);
-        ex_phi_small(x2, ex2, ph2);
-        if (fmaxf(x0, fmaxf(x1, x2)) >= kSeriesMax) {
-            ex_phi(x0, ex0, ph0);
-            ex_phi(x1, ex1, ph1);
-            ex_phi(x2, ex2, ph2);
+        ex_phi3(x0, x1, x2, ex0, ex1, ex2, ph0, ph1, ph2);
+        const float t0 = __builtin_amdgcn_exp2f(-p.L0 * kLog2e);
+        const float t1 = __builtin_amdgcn_exp2f(-p.L1 * kLog2e);
+        const float t2 = __builtin_amdgcn_exp2f(-p.L2 * kLog2e);
+        add_term<false, KAHAN>(p.C0, p.K0, 1.f, t0 * ((e0 * w) * ph0));
+        add_term<false, KAHAN>(p.C1, p.K1, 1.f, t1 * ((e1 * w) * ph1));
+        add_term<false, KAHAN>(p.C2, p.K2, 1.f, t2 * ((e2 * w) * ph2));
+        if (GEN) {
+            p.D0 = __builtin_fmaf(t0, x0 * ph0, p.D0);
+            p.D1 = __builtin_fmaf(t1, x1 * ph1, p.D1);
+            p.D2 = __builtin_fmaf(t2, x2 * ph2, p.D2);
         }
-        add_term<true, KAHAN>(C0, K0, T0, e0 * ph0);
-        add_term<true, KAHAN>(C1, K1, T1, e1 * ph1);
-        add_term<true, KAHAN>(C2, K2, T2, e2 * ph2);
-        T0 *= ex0;
-        T1 *= ex1;
-        T2 *= ex2;
+        p.L0 += x0;
+        p.L1 += x1;
+        p.L2 += x2;
+        (void)ex0;
+        (void)ex1;
+        (void)ex2;
+    }
+}
+
+// End of a pixel's list: adds the E = A absorbers' contribution,
+// (1 - exp(-L)) - D (0 when none covered the pixel), to C once,
+// compensated, and returns the transmittance exp(-L) per channel.
+template <bool ORDERED, bool KAHAN, bool GEN>
+__device__ __forceinline__ void finish(Px &p, float &T0, float &T1, float &T2) {
+#pragma clang fp contract(off)
+    T0 = T1 = T2 = 1.f;
+    if (!ORDERED) return;
+    float g0 = -expm1f(-p.L0), g1 = -expm1f(-p.L1), g2 = -expm1f(-p.L2);
+    T0 = expf(-p.L0);
+    T1 = expf(-p.L1);
+    T2 = expf(-p.L2);
+    if (GEN) {
+        const bool s = p.seen != 0.f;
+        g0 = s ? g0 - p.D0 : 0.f;
+        g1 = s ? g1 - p.D1 : 0.f;
+        g2 = s ? g2 - p.D2 : 0.f;
+    }
+    if (KAHAN) {
+        p.C0 = p.C0 + (g0 != 0.f ? g0 - p.K0 : 0.f);
+        p.C1 = p.C1 + (g1 != 0.f ? g1 - p.K1 : 0.f);
+        p.C2 = p.C2 + (g2 != 0.f ? g2 - p.K2 : 0.f);
+    } else {
+        p.C0 += g0;
+        p.C1 += g1;
+        p.C2 += g2;
     }
 }
 
@@ -146,6 +256,11 @@ __device__ __forceinline__ void write_pixel(const SplatArgs &a, int i, int j, fl
 constexpr uint32_t kEmitOnly = 0x80000000u;      // A = 0: emission only
 constexpr uint32_t kEmitEqAbsorb = 0x40000000u;  // E = A per channel (same colour terms)
 constexpr uint32_t kRowMask = 0x0FFFFFFFu;       // j0 | j1 << 14
+
+// Kind of a staged record from its flags.
+__device__ __forceinline__ int record_kind(uint32_t flags) {
+    return (flags & kEmitOnly) ? kKindEmit : ((flags & kEmitEqAbsorb) ? kKindEqual : kKindGeneral);
+}
 
 // One record as the compositing loop needs it: packed box (flags above),
 // membership fields, Gaussian
@@ -236,21 +351,6 @@ __device__ __forceinline__ Expanded expand_record(const SplatArgs &a, uint32_t i
     return expand_loaded(a, a.rec[idx].a, a.rec[idx].b, idx, vmin, vmax);
 }
 
-// Column of the density along a member pixel's ray per unit rho0, from the
-// squared distance d2 (pixels^2), the record's r2 = (f sigma_s)^2 and
-// qs = log2(e) / sigma_s^2: exp(-q^2), times erf(sqrt(f^2 - q^2)) when the
-// density is cut to the f sigma ball (f^2 - q^2 = (r2 - d2) / sigma_s^2).
-template <bool K3D>
-__device__ __forceinline__ float column_weight(float d2, float r2, float qs) {
-#pragma clang fp contract(off)
-    float w = __builtin_amdgcn_exp2f(-d2 * qs);
-    if (K3D) {
-        const float rem = fmaxf(r2 - d2, 0.0f) * (qs * 0.6931471805599453f);
-        w *= erff(sqrtf(rem));
-    }
-    return w;
-}
-
 // Records staged per batch: B indices of at most 8 bits per lane list.
 template <int T>
 struct Batch {
@@ -262,7 +362,7 @@ struct Batch {
 // builds, per lane, the ordered list of its member records in LDS; phase 2
 // walks the lists, so every active lane composites (full lane use, at the
 // price of per-lane LDS gathers).
-template <int T, bool ORDERED, bool KAHAN>
+template <int T, bool ORDERED, bool KAHAN, bool GEN>
 __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
     constexpr int NT = T * T;
     constexpr int B = Batch<T>::B;
@@ -300,9 +400,8 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
     __syncthreads();
 
     uint32_t n_member = 0, n_absorb = 0;
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
-    float T0 = 1.f, T1 = 1.f, T2 = 1.f;
+    Px px;
+    px_init(px);
 
     for (uint32_t base = start; base < end; base += B) {
         // stage: gather records, expand colours once per record
@@ -353,15 +452,12 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
                 const uint32_t b0 = s_b0[r], b1 = s_b1[r];
                 const int i0 = (int)(b0 & kBboxMask), j0 = (int)(b1 & kBboxMask);
                 const float d2 = member_d2(i, i0, s_ur[r], j, j0, s_vr[r]);
-                const float w = a.kernel3d ? column_weight<true>(d2, s_r2[r], s_qs[r])
-                                           : column_weight<false>(d2, s_r2[r], s_qs[r]);
+                const Col cw = a.kernel3d ? column<true>(d2, s_r2[r], s_qs[r])
+                                          : column<false>(d2, s_r2[r], s_qs[r]);
                 ++n_member;
                 if (ORDERED) n_absorb += (b1 >> 31) ^ 1u;
-                // emission-only records take the absorbing branch too: with
-                // A = 0 the series gives phi = 1 and exp(-x) = 1 exactly
-                composite<ORDERED, KAHAN>(false, w, s_e[0][r], s_e[1][r], s_e[2][r], s_a[0][r],
-                                          s_a[1][r], s_a[2][r], C0, C1, C2, K0, K1, K2, T0, T1,
-                                          T2);
+                composite<ORDERED, KAHAN, GEN>(record_kind(b1), cw, s_e[0][r], s_e[1][r],
+                                               s_e[2][r], s_a[0][r], s_a[1][r], s_a[2][r], px);
             }
         }
         __syncthreads();
@@ -388,13 +484,15 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
         if (t) atomicAdd(&a.member_count[2 * tile], t);
         if (ta) atomicAdd(&a.member_count[2 * tile + 1], ta);
     }
+    float T0, T1, T2;
+    finish<ORDERED, KAHAN, GEN>(px, T0, T1, T2);
     if (nseg == 1) {
-        write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
+        write_pixel<ORDERED>(a, i, j, px.C0, px.C1, px.C2, T0, T1, T2);
     } else if (a.part_off[tile] + seg < a.max_slots) {
         float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
-        slot[0 * NT + tid] = C0;
-        slot[1 * NT + tid] = C1;
-        slot[2 * NT + tid] = C2;
+        slot[0 * NT + tid] = px.C0;
+        slot[1 * NT + tid] = px.C1;
+        slot[2 * NT + tid] = px.C2;
         if (ORDERED) {
             slot[3 * NT + tid] = T0;
             slot[4 * NT + tid] = T1;
@@ -420,10 +518,11 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 // (exact), a in [1, 2 (i1 - i0) + 1] is the box test and
 // fma(1/2, a, -(u - i0)) rounds (i - i0 + 1/2) - (u - i0) once, which is
 // the binary32 offset of the index recipe bit for bit.
-template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D>
-__global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
+// One 8x8 block (sub) of one item: the body of the row walk, shared by the
+// per-view launch and the persistent multi-view launch.
+template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D, bool GEN>
+__device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uint32_t sub) {
     constexpr int NT = T * T;
-    constexpr int NW = NT / 64;  // 8x8 blocks per tile, one workgroup of one wave each
     constexpr int QW = T / 8;    // blocks per tile row
     constexpr uint32_t kB = 64;   // records staged per batch (one per lane)
     constexpr int kS = 1;         // 64-key chunks per scan
@@ -434,12 +533,6 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     __shared__ uint32_t s_q[kQ];
     __shared__ float s_vmin[kMaxSpecies], s_vmax[kMaxSpecies];
 
-    // Workgroups are dealt to the 8 XCDs round-robin.  In each XCD's own
-    // sequence k, the NW blocks of an item come one after another (they
-    // read the same keys and records, through that XCD's L2), items in runs
-    // of kRun.
-    const uint32_t b = blockIdx.x, k = (b >> 3) / NW, sub = (b >> 3) % NW;
-    const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
     if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
     const uint32_t tile = a.item_tile[item];
@@ -460,9 +553,8 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
     __syncthreads();
 
     uint32_t n_member = 0, n_absorb = 0;  // this lane's contributions
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    float K0 = 0.f, K1 = 0.f, K2 = 0.f;  // compensation terms
-    float T0 = 1.f, T1 = 1.f, T2 = 1.f;
+    Px px;
+    px_init(px);
 
     // Keys and values of the next 64 kS positions are loaded one scan ahead,
     // at positions clamped to the segment's last pair (always valid).
@@ -554,16 +646,18 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
             const bool emit_only = (flags & kEmitOnly) != 0;
             if (!in) return;
             if (COUNT) ++n_member;
-            const float w = column_weight<K3D>(d2, f.z, f.w);
+            const Col cw = column<K3D>(d2, f.z, f.w);
             if (!ORDERED || emit_only) {
-                composite<ORDERED, KAHAN>(true, w, e.x, e.y, e.z, 0.f, 0.f, 0.f, C0, C1, C2, K0,
-                                          K1, K2, T0, T1, T2);
+                composite<ORDERED, KAHAN, GEN>(kKindEmit, cw, e.x, e.y, e.z, 0.f, 0.f, 0.f, px);
+            } else if (flags & kEmitEqAbsorb) {
+                if (COUNT) ++n_absorb;
+                // E = A: only the optical depth is carried
+                composite<ORDERED, KAHAN, GEN>(kKindEqual, cw, e.x, e.y, e.z, 0.f, 0.f, 0.f, px);
             } else {
                 if (COUNT) ++n_absorb;
-                // E = A: the emission row doubles as the absorption row
-                const float4 x = s_r[(flags & kEmitEqAbsorb) ? 2 : 3][r];
-                composite<ORDERED, KAHAN>(false, w, e.x, e.y, e.z, x.x, x.y, x.z, C0, C1, C2, K0,
-                                          K1, K2, T0, T1, T2);
+                const float4 x = s_r[3][r];
+                composite<ORDERED, KAHAN, GEN>(kKindGeneral, cw, e.x, e.y, e.z, x.x, x.y, x.z,
+                                               px);
             }
         };
         // four visits per trip: the register allocator rotates the running
@@ -593,19 +687,72 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
         if (n_member) atomicAdd(&a.member_count[2 * tile], (unsigned long long)n_member);
         if (n_absorb) atomicAdd(&a.member_count[2 * tile + 1], (unsigned long long)n_absorb);
     }
+    float T0, T1, T2;
+    finish<ORDERED, KAHAN, GEN>(px, T0, T1, T2);
     if (nseg == 1) {
-        write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
+        write_pixel<ORDERED>(a, i, j, px.C0, px.C1, px.C2, T0, T1, T2);
     } else if (a.part_off[tile] + seg < a.max_slots) {
         const int p = (j - ty0) * T + (i - tx0);
         float *slot = a.partial + (size_t)(a.part_off[tile] + seg) * 6 * NT;
-        slot[0 * NT + p] = C0;
-        slot[1 * NT + p] = C1;
-        slot[2 * NT + p] = C2;
+        slot[0 * NT + p] = px.C0;
+        slot[1 * NT + p] = px.C1;
+        slot[2 * NT + p] = px.C2;
         if (ORDERED) {
             slot[3 * NT + p] = T0;
             slot[4 * NT + p] = T1;
             slot[5 * NT + p] = T2;
         }
+    }
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin.  In each XCD's own
+// sequence k, the NW blocks of an item come one after another (they read
+// the same keys and records, through that XCD's L2), items in runs of kRun.
+template <int T>
+__device__ __forceinline__ void unit_of(uint32_t b, uint32_t *item, uint32_t *sub,
+                                        uint32_t *run_base) {
+    constexpr uint32_t NW = (uint32_t)(T * T / 64);
+    const uint32_t k = (b >> 3) / NW;
+    *sub = (b >> 3) % NW;
+    *run_base = (k / kRun) * (8 * kRun);
+    *item = *run_base + (b & 7) * kRun + (k % kRun);
+}
+
+template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D, bool GEN>
+__global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
+    uint32_t item, sub, base;
+    unit_of<T>(blockIdx.x, &item, &sub, &base);
+    rows_unit<T, ORDERED, KAHAN, COUNT, K3D, GEN>(a, item, sub);
+}
+
+// Persistent row walk over the items of several views at once: the views'
+// settings sit in device memory, their item counts are read on the device,
+// and each workgroup takes units (item, 8x8 block) of the concatenated item
+// sequence in the same XCD-aware order as the per-view launch until none
+// is left.
+template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D, bool GEN>
+__global__ __launch_bounds__(64) void k_splat_rows_multi(const SplatArgs *views, int nv) {
+    uint32_t first[kMaxGroup + 1];
+    first[0] = 0;
+    for (int v = 0; v < kMaxGroup; ++v) {
+        uint32_t n = 0;
+        if (v < nv) {
+            const SplatArgs &a = views[v];
+            const uint64_t items = a.seg_off[(uint32_t)(a.ntx * a.nty)];
+            n = (uint32_t)(items < a.max_items ? items : a.max_items);
+        }
+        first[v + 1] = first[v] + n;
+    }
+    const uint32_t total = first[nv];
+    for (uint32_t b = blockIdx.x;; b += gridDim.x) {
+        uint32_t item, sub, base;
+        unit_of<T>(b, &item, &sub, &base);
+        if (base >= total) break;
+        if (item >= total) continue;
+        int v = 0;
+        while (v + 1 < nv && item >= first[v + 1]) ++v;
+        rows_unit<T, ORDERED, KAHAN, COUNT, K3D, GEN>(views[v], item - first[v], sub);
+        __syncthreads();  // the next unit reuses the staging rows
     }
 }
 
@@ -628,14 +775,16 @@ __device__ __forceinline__ int state_index(int x, int y) {
     return y * T + (x ^ sw);
 }
 
-template <int T, bool ORDERED, bool KAHAN>
+template <int T, bool ORDERED, bool KAHAN, bool GEN>
 __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
     constexpr int NT = T * T;
     constexpr int NS = ORDERED ? NT : 1;
     constexpr int NK = KAHAN ? NT : 1;
+    constexpr int NG = GEN ? NT : 1;
     __shared__ float s_C[3][NT];
-    __shared__ float s_T[3][NS];
+    __shared__ float s_T[3][NS];  // optical depth L per channel
     __shared__ float s_K[3][NK];
+    __shared__ float s_D[4][NG];  // D per channel, then the E = A flag
     // staged records, three 16-byte rows each: {b0, b1, ur, vr},
     // {r2, qs, e0, e1}, {e2, a0, a1, a2}
     __shared__ uint4 s_rec[3][64];
@@ -661,14 +810,20 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
         s_C[1][p] = 0.f;
         s_C[2][p] = 0.f;
         if (ORDERED) {
-            s_T[0][p] = 1.f;
-            s_T[1][p] = 1.f;
-            s_T[2][p] = 1.f;
+            s_T[0][p] = 0.f;  // optical depth
+            s_T[1][p] = 0.f;
+            s_T[2][p] = 0.f;
         }
         if (KAHAN) {
             s_K[0][p] = 0.f;
             s_K[1][p] = 0.f;
             s_K[2][p] = 0.f;
+        }
+        if (GEN) {
+            s_D[0][p] = 0.f;
+            s_D[1][p] = 0.f;
+            s_D[2][p] = 0.f;
+            s_D[3][p] = 0.f;
         }
     }
     __syncthreads();
@@ -703,6 +858,7 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
             const float ur = __uint_as_float(q0.z), vr = __uint_as_float(q0.w);
             const float r2 = __uint_as_float(q1.x), qs = __uint_as_float(q1.y);
             const bool emit_only = (b1 >> 31) != 0;
+            const int kind = record_kind(b1);
             for (int y0 = cj0; y0 <= cj1; y0 += 64 >> gs) {
                 const int j = y0 + ly;
                 if (!col_in || j > cj1) continue;
@@ -710,38 +866,51 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
                 if (!(d2 <= r2)) continue;
                 ++n_member;
                 if (ORDERED && !emit_only) ++n_absorb;
-                const float w = a.kernel3d ? column_weight<true>(d2, r2, qs)
-                                           : column_weight<false>(d2, r2, qs);
+                const Col cw = a.kernel3d ? column<true>(d2, r2, qs) : column<false>(d2, r2, qs);
                 const int o = state_index<T>(i - tx0, j - ty0);
-                float C0 = s_C[0][o], C1 = s_C[1][o], C2 = s_C[2][o];
-                float T0 = 1.f, T1 = 1.f, T2 = 1.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
+                Px px;
+                px_init(px);
+                px.C0 = s_C[0][o];
+                px.C1 = s_C[1][o];
+                px.C2 = s_C[2][o];
                 if (ORDERED) {
-                    T0 = s_T[0][o];
-                    T1 = s_T[1][o];
-                    T2 = s_T[2][o];
+                    px.L0 = s_T[0][o];
+                    px.L1 = s_T[1][o];
+                    px.L2 = s_T[2][o];
                 }
                 if (KAHAN) {
-                    K0 = s_K[0][o];
-                    K1 = s_K[1][o];
-                    K2 = s_K[2][o];
+                    px.K0 = s_K[0][o];
+                    px.K1 = s_K[1][o];
+                    px.K2 = s_K[2][o];
                 }
-                composite<ORDERED, KAHAN>(emit_only, w, __uint_as_float(q1.z),
-                                          __uint_as_float(q1.w), __uint_as_float(q2.x),
-                                          __uint_as_float(q2.y), __uint_as_float(q2.z),
-                                          __uint_as_float(q2.w), C0, C1, C2, K0, K1, K2, T0, T1,
-                                          T2);
-                s_C[0][o] = C0;
-                s_C[1][o] = C1;
-                s_C[2][o] = C2;
+                if (GEN) {
+                    px.D0 = s_D[0][o];
+                    px.D1 = s_D[1][o];
+                    px.D2 = s_D[2][o];
+                    px.seen = s_D[3][o];
+                }
+                composite<ORDERED, KAHAN, GEN>(kind, cw, __uint_as_float(q1.z),
+                                               __uint_as_float(q1.w), __uint_as_float(q2.x),
+                                               __uint_as_float(q2.y), __uint_as_float(q2.z),
+                                               __uint_as_float(q2.w), px);
+                s_C[0][o] = px.C0;
+                s_C[1][o] = px.C1;
+                s_C[2][o] = px.C2;
                 if (ORDERED) {
-                    s_T[0][o] = T0;
-                    s_T[1][o] = T1;
-                    s_T[2][o] = T2;
+                    s_T[0][o] = px.L0;
+                    s_T[1][o] = px.L1;
+                    s_T[2][o] = px.L2;
                 }
                 if (KAHAN) {
-                    s_K[0][o] = K0;
-                    s_K[1][o] = K1;
-                    s_K[2][o] = K2;
+                    s_K[0][o] = px.K0;
+                    s_K[1][o] = px.K1;
+                    s_K[2][o] = px.K2;
+                }
+                if (GEN) {
+                    s_D[0][o] = px.D0;
+                    s_D[1][o] = px.D1;
+                    s_D[2][o] = px.D2;
+                    s_D[3][o] = px.seen;
                 }
             }
             // the next record may map another lane onto these pixels: keep
@@ -765,9 +934,30 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
     for (int p = lane; p < NT; p += 64) {
         const int x = p % T, y = p / T;
         const int o = state_index<T>(x, y);
-        const float C0 = s_C[0][o], C1 = s_C[1][o], C2 = s_C[2][o];
-        const float T0 = ORDERED ? s_T[0][o] : 1.f, T1 = ORDERED ? s_T[1][o] : 1.f,
-                    T2 = ORDERED ? s_T[2][o] : 1.f;
+        Px px;
+        px_init(px);
+        px.C0 = s_C[0][o];
+        px.C1 = s_C[1][o];
+        px.C2 = s_C[2][o];
+        if (ORDERED) {
+            px.L0 = s_T[0][o];
+            px.L1 = s_T[1][o];
+            px.L2 = s_T[2][o];
+        }
+        if (KAHAN) {
+            px.K0 = s_K[0][o];
+            px.K1 = s_K[1][o];
+            px.K2 = s_K[2][o];
+        }
+        if (GEN) {
+            px.D0 = s_D[0][o];
+            px.D1 = s_D[1][o];
+            px.D2 = s_D[2][o];
+            px.seen = s_D[3][o];
+        }
+        float T0, T1, T2;
+        finish<ORDERED, KAHAN, GEN>(px, T0, T1, T2);
+        const float C0 = px.C0, C1 = px.C1, C2 = px.C2;
         if (nseg == 1) {
             write_pixel<ORDERED>(a, tx0 + x, ty0 + y, C0, C1, C2, T0, T1, T2);
         } else if (a.part_off[tile] + seg < a.max_slots) {
@@ -788,30 +978,31 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
 // C += Tr * C_s, Tr *= Tr_s (the associative "over"); a plain sum when
 // nothing absorbs.
 template <int T, bool ORDERED, bool KAHAN>
-__global__ __launch_bounds__(T *T) void k_merge(SplatArgs a) {
+__global__ __launch_bounds__(T *T < 1024 ? T *T : 1024) void k_merge(SplatArgs a) {
     constexpr int NT = T * T;
     const uint32_t tile = blockIdx.x;
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     if (nseg <= 1 || (a.tile_mask && !a.tile_mask[tile])) return;
     if (a.part_off[tile] + nseg > a.max_slots) return;  // never: the slot bound holds
     const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
-    const int tid = threadIdx.x;
-    const int i = tx * T + (tid % T), j = ty * T + (tid / T);
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
-    float T0 = 1.f, T1 = 1.f, T2 = 1.f;
-    const float *slot = a.partial + (size_t)a.part_off[tile] * 6 * NT;
-    for (uint32_t s = 0; s < nseg; ++s, slot += 6 * NT) {
-        const float c0 = slot[tid], c1 = slot[NT + tid], c2 = slot[2 * NT + tid];
-        add_term<ORDERED, KAHAN>(C0, K0, T0, c0);
-        add_term<ORDERED, KAHAN>(C1, K1, T1, c1);
-        add_term<ORDERED, KAHAN>(C2, K2, T2, c2);
-        if (ORDERED) {
-            T0 *= slot[3 * NT + tid];
-            T1 *= slot[4 * NT + tid];
-            T2 *= slot[5 * NT + tid];
+    for (int p = threadIdx.x; p < NT; p += blockDim.x) {
+        const int i = tx * T + (p % T), j = ty * T + (p / T);
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, K0 = 0.f, K1 = 0.f, K2 = 0.f;
+        float T0 = 1.f, T1 = 1.f, T2 = 1.f;
+        const float *slot = a.partial + (size_t)a.part_off[tile] * 6 * NT;
+        for (uint32_t s = 0; s < nseg; ++s, slot += 6 * NT) {
+            const float c0 = slot[p], c1 = slot[NT + p], c2 = slot[2 * NT + p];
+            add_term<ORDERED, KAHAN>(C0, K0, T0, c0);
+            add_term<ORDERED, KAHAN>(C1, K1, T1, c1);
+            add_term<ORDERED, KAHAN>(C2, K2, T2, c2);
+            if (ORDERED) {
+                T0 *= slot[3 * NT + p];
+                T1 *= slot[4 * NT + p];
+                T2 *= slot[5 * NT + p];
+            }
         }
+        write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
     }
-    write_pixel<ORDERED>(a, i, j, C0, C1, C2, T0, T1, T2);
 }
 
 __global__ void k_seg_count(const uint32_t *ts, const uint32_t *te, uint32_t n_tiles,
@@ -837,7 +1028,7 @@ __global__ void k_item_tiles(const uint64_t *seg_off, uint32_t n_tiles, uint32_t
     for (uint64_t k = seg_off[t]; k < e; ++k) item_tile[k] = t;
 }
 
-template <int T, bool ORDERED, bool KAHAN>
+template <int T, bool ORDERED, bool KAHAN, bool GEN>
 hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
     switch (a.variant) {
         case kSplatRows: {
@@ -845,46 +1036,141 @@ hipError_t launch_tok(const SplatArgs &a, uint32_t grid, hipStream_t s) {
             const dim3 g(grid * (T * T / 64)), b(64);
             if (a.kernel3d) {
                 if (a.count)
-                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true, true>), g, b, 0, s,
-                                       a);
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true, true, GEN>), g, b,
+                                       0, s, a);
                 else
-                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false, true>), g, b, 0,
-                                       s, a);
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false, true, GEN>), g, b,
+                                       0, s, a);
             } else {
                 if (a.count)
-                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true, false>), g, b, 0,
-                                       s, a);
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, true, false, GEN>), g, b,
+                                       0, s, a);
                 else
-                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false, false>), g, b, 0,
-                                       s, a);
+                    hipLaunchKernelGGL((k_splat_rows<T, ORDERED, KAHAN, false, false, GEN>), g,
+                                       b, 0, s, a);
             }
             break;
         }
-        case kSplatLists:
-            hipLaunchKernelGGL((k_splat_lists<T, ORDERED, KAHAN>), dim3(grid), dim3(T * T), 0, s,
-                               a);
-            break;
         default:
-            hipLaunchKernelGGL((k_splat_box<T, ORDERED, KAHAN>), dim3(grid), dim3(64), 0, s, a);
+            // member lists and box-mapped lanes hold a whole tile in one
+            // workgroup: up to 32 px tiles
+            if constexpr (T <= 32) {
+                if (a.variant == kSplatLists)
+                    hipLaunchKernelGGL((k_splat_lists<T, ORDERED, KAHAN, GEN>), dim3(grid),
+                                       dim3(T * T), 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_splat_box<T, ORDERED, KAHAN, GEN>), dim3(grid), dim3(64),
+                                       0, s, a);
+            } else {
+                return hipErrorInvalidValue;
+            }
             break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_merge<T, ORDERED, KAHAN>), dim3((uint32_t)(a.ntx * a.nty)), dim3(T * T),
-                       0, s, a);
+    hipLaunchKernelGGL((k_merge<T, ORDERED, KAHAN>), dim3((uint32_t)(a.ntx * a.nty)),
+                       dim3(T * T < 1024 ? T * T : 1024), 0, s, a);
     return hipGetLastError();
 }
 
 template <int T>
 hipError_t launch_t(const SplatArgs &a, uint32_t grid, hipStream_t s) {
-    if (a.ordered)
-        return a.compensated ? launch_tok<T, true, true>(a, grid, s)
-                             : launch_tok<T, true, false>(a, grid, s);
-    return a.compensated ? launch_tok<T, false, true>(a, grid, s)
-                         : launch_tok<T, false, false>(a, grid, s);
+    // absorbers with E != A exist only in ordered sets
+    if (a.ordered) {
+        if (a.general)
+            return a.compensated ? launch_tok<T, true, true, true>(a, grid, s)
+                                 : launch_tok<T, true, false, true>(a, grid, s);
+        return a.compensated ? launch_tok<T, true, true, false>(a, grid, s)
+                             : launch_tok<T, true, false, false>(a, grid, s);
+    }
+    return a.compensated ? launch_tok<T, false, true, false>(a, grid, s)
+                         : launch_tok<T, false, false, false>(a, grid, s);
+}
+
+__global__ void k_store_args(SplatArgs a, SplatArgs *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
+}
+
+template <int T, bool ORDERED, bool KAHAN, bool GEN>
+hipError_t launch_multi_tok(const SplatArgs *views, int nv, const SplatArgs &a, hipStream_t s) {
+    // a persistent grid: 8 single-wave workgroups per SIMD, a multiple of 8
+    const dim3 g(256 * 4 * 8), b(64);
+    if (a.kernel3d) {
+        if (a.count)
+            hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, true, true, GEN>), g, b, 0, s,
+                               views, nv);
+        else
+            hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, false, true, GEN>), g, b, 0,
+                               s, views, nv);
+    } else {
+        if (a.count)
+            hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, true, false, GEN>), g, b, 0,
+                               s, views, nv);
+        else
+            hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, false, false, GEN>), g, b, 0,
+                               s, views, nv);
+    }
+    return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_multi_t(const SplatArgs *views, int nv, const SplatArgs &a, hipStream_t s) {
+    if (a.ordered) {
+        if (a.general)
+            return a.compensated ? launch_multi_tok<T, true, true, true>(views, nv, a, s)
+                                 : launch_multi_tok<T, true, false, true>(views, nv, a, s);
+        return a.compensated ? launch_multi_tok<T, true, true, false>(views, nv, a, s)
+                             : launch_multi_tok<T, true, false, false>(views, nv, a, s);
+    }
+    return a.compensated ? launch_multi_tok<T, false, true, false>(views, nv, a, s)
+                         : launch_multi_tok<T, false, false, false>(views, nv, a, s);
+}
+
+template <int T>
+hipError_t launch_merge_t(const SplatArgs &a, hipStream_t s) {
+    const dim3 g((uint32_t)(a.ntx * a.nty)), b(T * T < 1024 ? T * T : 1024);
+    if (a.ordered) {
+        if (a.compensated)
+            hipLaunchKernelGGL((k_merge<T, true, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_merge<T, true, false>), g, b, 0, s, a);
+    } else {
+        if (a.compensated)
+            hipLaunchKernelGGL((k_merge<T, false, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_merge<T, false, false>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t store_splat_args(const SplatArgs &a, SplatArgs *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_store_args, dim3(1), dim3(64), 0, s, a, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat_multi(const SplatArgs *views, int nv, const SplatArgs &a,
+                              hipStream_t s) {
+    if (nv < 1 || nv > kMaxGroup || a.variant != kSplatRows) return hipErrorInvalidValue;
+    switch (a.tile) {
+        case 8: return launch_multi_t<8>(views, nv, a, s);
+        case 16: return launch_multi_t<16>(views, nv, a, s);
+        case 32: return launch_multi_t<32>(views, nv, a, s);
+        case 64: return launch_multi_t<64>(views, nv, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_merge(const SplatArgs &a, hipStream_t s) {
+    switch (a.tile) {
+        case 8: return launch_merge_t<8>(a, s);
+        case 16: return launch_merge_t<16>(a, s);
+        case 32: return launch_merge_t<32>(a, s);
+        case 64: return launch_merge_t<64>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 uint32_t splat_grid(uint32_t n_tiles, uint64_t npairs, uint32_t seg_len) {
     const uint64_t items = (uint64_t)n_tiles + (npairs + seg_len - 1) / seg_len;
@@ -915,6 +1201,7 @@ hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s) {
         case 8: return launch_t<8>(a, grid, s);
         case 16: return launch_t<16>(a, grid, s);
         case 32: return launch_t<32>(a, grid, s);
+        case 64: return launch_t<64>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -133,7 +133,8 @@ def test_perspective_needs_positive_near_and_focal():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(sigma_over_h=0.0), 1), (dict(trunc_f=-1.0), 1), (dict(tile=12), 4), (dict(tile=64), 4),
+    (dict(sigma_over_h=0.0), 1), (dict(trunc_f=-1.0), 1), (dict(tile=12), 4), (dict(tile=128), 4),
+    (dict(tile=64), 0), (dict(tile=64, splat_variant=2), 4), (dict(tile=64, splat_variant=3), 4),
     (dict(splat_variant=4), 1), (dict(splat_variant=-1), 1), (dict(splat_variant=3), 0),
     (dict(seg_records=-5), 1), (dict(batch_streams=5), 1), (dict(batch_streams=-1), 1),
     (dict(batch_streams=4), 0), (dict(kernel=2), 1), (dict(kernel=-1), 1), (dict(kernel=1), 0),

@@ -448,3 +448,19 @@ def test_c2_full_size_sampled(torch_cuda, orc):
     rel = np.abs(got - ref).max(axis=0) / np.where(scale > 0, scale, 1)
     assert np.all(rel <= TOL), rel
     assert st["n_visible"] > 7_000_000  # the 16:9 frame crops the box top and bottom
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_small", "edges"])
+def test_tile64_row_walk(torch_cuda, orc, name):
+    """64 px tiles (row walk only: 64 single-wave workgroups per tile, no
+    block masks in the keys) against the oracle, whole and in chunks."""
+    scene = {"c1": lambda: c1(60_000, seed=13), "c2_small": lambda: c2_small(80_000, seed=14),
+             "edges": edge_scene}[name]()
+    ref = orc.render(scene)
+    img, st = gpu_render(scene, tile=64, compensated=True, stats=True)
+    assert st["tile"] == 64
+    check_image(img, ref)
+    img, st = gpu_render(scene, tile=64, max_pairs=max(64, st["n_pairs"] // 4), seg_records=64,
+                         stats=True)
+    assert st["n_chunks"] > 1
+    check_image(img, ref)
