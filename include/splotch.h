@@ -515,7 +515,8 @@ splotch_status splotch_nn_f32_to_bf16(const float *in, uint16_t *out, int64_t n,
  * (FP32 master weights and biases, their gradients, Adam moments, BF16
  * copies); activations in a caller-owned workspace of
  * splotch_nn_workspace_bytes for the batch shape (n images of h x w, h and
- * w multiples of 2^(n_levels-1)).  The object itself is host memory; it is
+ * w multiples of 2^(n_levels-1), n h w below 2^31; other shapes are
+ * SPLOTCH_E_INVALID_ARG).  The object itself is host memory; it is
  * not thread-safe.  All device work is asynchronous on `stream` except
  * create, save and load, which wait for their copies.
  * ------------------------------------------------------------------------ */

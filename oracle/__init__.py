@@ -29,7 +29,7 @@ VISIBLE, INVALID, DEPTH, OFFSCREEN = 0, 1, 2, 3
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, IEEE semantics)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"  # concurrent builders do not share it
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
                                "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)

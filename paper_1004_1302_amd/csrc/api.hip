@@ -27,7 +27,7 @@ static_assert(kMaxLanes <= kMaxGroup, "a persistent group holds one view per lan
 struct Layout {
     size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
     size_t tstart, tend, mcount, seg_len, nseg, nmulti, seg_off, part_off, seg_scan, item_tile;
-    size_t partial, flags, sargs, split, split_cnt;
+    size_t partial, flags, sargs, unit_next, split, split_cnt;
     size_t pk0, pk1, pv0, pv1;
     uint64_t max_items, max_slots;
     size_t total;
@@ -91,6 +91,7 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
     L.seg_len = take(4);
     L.flags = take((size_t)SPLOTCH_MAX_VIEWS * 12);  // per view: overflow flag (u32), pairs (u64)
     L.sargs = take(kMaxGroup * sizeof(SplatArgs));    // splat settings of a persistent group
+    L.unit_next = take(kUnitCounters * 4);            // its per-XCD unit counters
     L.nseg = take((size_t)L.n_tiles * 4);
     L.nmulti = take((size_t)L.n_tiles * 4);
     L.seg_off = take(((size_t)L.n_tiles + 1) * 8);
@@ -752,13 +753,25 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         sa.compensated = p->compensated ? 1 : 0;
         sa.ordered = c.L.ordered ? 1 : 0;
         sa.variant = splat_variant_of(p->splat_variant);
+        // a view that overflowed writes nothing (it is rendered again in
+        // chunks, or reported)
+        sa.skip = flags + v;
         if (defer) {
             *defer = sa;
             return SPLOTCH_OK;
         }
-        const uint32_t q = 64;
-        const uint32_t grid = (uint32_t)((Lv.n_tiles + kSegTarget + q - 1) / q * q);
-        TRY(launch_splat(sa, grid, c.s));
+        if (sa.variant == kSplatRows) {
+            // the item count is on the device: a persistent launch over
+            // the view's units instead of a grid sized to the most items
+            SplatArgs *dev = c.at<SplatArgs>(c.L.sargs);
+            TRY(store_splat_args(sa, dev, c.s));
+            TRY(launch_splat_multi(dev, 1, sa, c.at<uint32_t>(c.L.unit_next), c.s));
+            TRY(launch_merge(sa, c.s));
+        } else {
+            const uint32_t q = 64;
+            const uint32_t grid = (uint32_t)((Lv.n_tiles + kSegTarget + q - 1) / q * q);
+            TRY(launch_splat(sa, grid, c.s));
+        }
     }
     return SPLOTCH_OK;
 }
@@ -800,7 +813,7 @@ splotch_status enqueue_batch(std::vector<Ctx> &lanes, const LaneSet *ls,
                     TRY(hipStreamWaitEvent(c0.s, ls->join[k - 1], 0));
                 }
             }
-            TRY(launch_splat_multi(views, G, sa[0], c0.s));
+            TRY(launch_splat_multi(views, G, sa[0], c0.at<uint32_t>(c0.L.unit_next), c0.s));
             for (int k = 0; k < G; ++k) TRY(launch_merge(sa[k], c0.s));
         }
         return SPLOTCH_OK;
@@ -1113,7 +1126,12 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
         }
         TRY(hipGraphLaunch(it->exec, c.s));
     }
-    if (!p->stats) return SPLOTCH_OK;
+    // Eager batches wait for the overflow flags: a view whose pairs exceeded
+    // the capacity wrote nothing and is rendered again here in
+    // workspace-bounded chunks, as splotch_render does.  A graph replay
+    // cannot branch on them: without stats it returns at once, with stats
+    // it reports the overflowed views.
+    if (use_graph && !p->stats) return SPLOTCH_OK;
     std::vector<uint32_t> fl(n_views);
     std::vector<uint64_t> tot(n_views);
     uint32_t *flags = c.at<uint32_t>(c.L.flags);
@@ -1123,13 +1141,23 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
     TRY(hipStreamSynchronize(c.s));
     bool over = false;
     for (int32_t v = 0; v < n_views; ++v) {
-        splotch_stats *s = &p->stats[v];
-        memset(s, 0, sizeof *s);
-        s->n_pairs = (int64_t)tot[v];
-        s->n_chunks = fl[v] ? 0 : 1;
-        s->tile = c.L.tile;
-        s->ordered = c.L.ordered ? 1 : 0;
-        over = over || fl[v];
+        splotch_stats one;
+        memset(&one, 0, sizeof one);
+        one.n_pairs = (int64_t)tot[v];
+        one.n_chunks = fl[v] ? 0 : 1;
+        one.tile = c.L.tile;
+        one.ordered = c.L.ordered ? 1 : 0;
+        if (fl[v] && !use_graph) {
+            // lane 0's part of the workspace: the pair capacity of one view
+            splotch_params r = q;
+            r.stats = p->stats ? &one : nullptr;
+            r.batch_streams = 0;
+            r.batch_persistent = 0;
+            r.profile = 0;
+            if ((st = splotch_render(P, &cams[v], cmap, &r, &images[v])) != SPLOTCH_OK) return st;
+        }
+        over = over || one.n_chunks == 0;
+        if (p->stats) p->stats[v] = one;
     }
     return over ? SPLOTCH_E_CAPACITY : SPLOTCH_OK;
 }

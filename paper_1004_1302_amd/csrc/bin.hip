@@ -218,7 +218,10 @@ hipError_t launch_tile_ranges(const uint32_t *sorted_keys, size_t n_pairs,
     if (e != hipSuccess) return e;
     e = launch_fill_u32(end, 0u, n_tiles, s);
     if (e != hipSuccess || n_pairs == 0) return e;
-    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for((n_pairs + 3) / 4, 1u << 20)), dim3(kThreads), 0, s,
+    // a count on the device (capacity-sized arrays): a capped grid strides
+    // over the live pairs
+    const unsigned cap = n_pairs_dev ? 8192u : (1u << 20);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for((n_pairs + 3) / 4, cap)), dim3(kThreads), 0, s,
                        sorted_keys, n_pairs, n_pairs_dev, start, end, n_tiles, key_mask);
     return hipGetLastError();
 }

@@ -209,6 +209,8 @@ struct SplatArgs {
     int accumulate, compensated, ordered;
     int variant;  // kSplatBox, kSplatRows or kSplatLists (see splat.hip)
     int count;    // 1: accumulate the member statistics (the row walk skips them otherwise)
+    const uint32_t *skip;  // device flag or null: nonzero = write nothing (a batched view
+                           // whose pairs overflowed the capacity)
 };
 // How a workgroup walks a tile's list.
 constexpr int kSplatBox = 0, kSplatRows = 1, kSplatLists = 2;
@@ -239,10 +241,13 @@ hipError_t launch_splat(const SplatArgs &a, uint32_t grid, hipStream_t s);
 // holds the settings that pick the kernel (tile, ordering, compensation,
 // counting, column kernel) and must match every view's.  The views' merge
 // kernels follow separately (launch_merge).
+// Work is handed out dynamically: next (kUnitCounters uint32, device) holds
+// one unit counter per XCD, cleared by the launcher.
 constexpr int kMaxGroup = 4;
+constexpr int kUnitCounters = 8;
 hipError_t store_splat_args(const SplatArgs &a, SplatArgs *dst, hipStream_t s);
 hipError_t launch_splat_multi(const SplatArgs *views, int nv, const SplatArgs &like,
-                              hipStream_t s);
+                              uint32_t *next, hipStream_t s);
 hipError_t launch_merge(const SplatArgs &a, hipStream_t s);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

@@ -7,6 +7,8 @@
 // offset per digit), then the scatter kernel ranks keys inside the tile
 // (wave ballots find equal digits, lanes in order, waves in order: stable),
 // reorders the tile in LDS and writes each digit run contiguously.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace splotch {
@@ -17,6 +19,7 @@ constexpr int kT = 256;
 constexpr int kW = kT / 64;
 constexpr int kIpt = 16;
 constexpr int kTile = kT * kIpt;  // 4096
+constexpr uint32_t kStrideGrid = 2048;  // workgroups of a pass sized on the device
 
 __device__ __forceinline__ uint32_t shfl_up_u32(uint32_t v, int o) {
     return (uint32_t)__shfl_up((int)v, o, 64);
@@ -190,50 +193,84 @@ __device__ __forceinline__ uint32_t tag_value(uint32_t idx, uint32_t count) {
     return idx | (code << kTagShift);
 }
 
+// Tiles of a radix pass.  With the element count known on the host the
+// grid has one workgroup per tile.  With a count on the device (batched
+// views: the pair arrays are sized to their capacity) the grid is capped
+// and each workgroup strides over the tiles; the live tiles are those the
+// device count fills, and the XCD-contiguous order is taken over them, so
+// every XCD shares the live work.  The capacity's other tiles need only
+// zero histogram columns.
+struct PassTiles {
+    uint32_t live;  // tiles holding elements
+    uint32_t all;   // tiles of the capacity (the histogram's columns)
+    __device__ PassTiles(size_t n_live, uint32_t nblocks) {
+        const size_t t = (n_live + kTile - 1) / kTile;
+        live = t < nblocks ? (uint32_t)t : nblocks;
+        all = nblocks;
+    }
+    // tile of stride position b (b < live: XCD-contiguous among the live)
+    __device__ uint32_t tile(uint32_t b) const {
+        return b < live ? xcd_contiguous(b, live) : b;
+    }
+};
+
 // Digit histogram of one tile.  16 copies of the counters (by lane mod 16)
 // keep a wave whose keys share a digit from serialising on one LDS address.
 constexpr int kHistCopies = 16;
 
+// STRIDE: the grid strides over the tiles (a count on the device); else one
+// workgroup per tile.
+template <bool STRIDE>
 __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_cap,
                                                 const uint64_t *n_dev, int shift, uint32_t bias,
                                                 uint32_t *hist, uint32_t nblocks) {
     const size_t n = live_count(n_cap, n_dev);
+    const PassTiles pt(n, nblocks);
     __shared__ uint32_t sh[kHistCopies][256];
-    for (int d = threadIdx.x; d < kHistCopies * 256; d += kT) (&sh[0][0])[d] = 0;
-    __syncthreads();
     const int c = threadIdx.x & (kHistCopies - 1);
-    // neighbouring tiles' counts share lines of the digit-major histogram
-    const uint32_t t = xcd_contiguous(blockIdx.x, nblocks);
-    const size_t base = (size_t)t * kTile;
+    for (uint32_t b = blockIdx.x; b < pt.all; b += STRIDE ? gridDim.x : pt.all) {
+        // neighbouring tiles' counts share lines of the digit-major histogram
+        const uint32_t t = pt.tile(b);
+        if (b >= pt.live) {
+            hist[(size_t)threadIdx.x * nblocks + t] = 0u;
+            continue;
+        }
+        for (int d = threadIdx.x; d < kHistCopies * 256; d += kT) (&sh[0][0])[d] = 0;
+        __syncthreads();
+        const size_t base = (size_t)t * kTile;
 #pragma unroll
-    for (int q = 0; q < kIpt; ++q) {
-        size_t idx = base + (size_t)q * kT + threadIdx.x;
-        if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & 255u], 1u);
+        for (int q = 0; q < kIpt; ++q) {
+            size_t idx = base + (size_t)q * kT + threadIdx.x;
+            if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
+        hist[(size_t)threadIdx.x * nblocks + t] = sum;
+        if (!STRIDE) break;
+        __syncthreads();  // before the next tile clears the counters
     }
-    __syncthreads();
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
-    hist[(size_t)threadIdx.x * nblocks + t] = sum;
 }
 
-__global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
-                                                   uint32_t *kout, uint32_t *vout, size_t n_cap,
-                                                   const uint64_t *n_dev, int shift,
-                                                   uint32_t bias, const uint32_t *hist,
-                                                   uint32_t nblocks, int write_keys,
-                                                   const uint32_t *tag) {
-    const size_t n = live_count(n_cap, n_dev);
-    // the runs two neighbouring tiles write for one digit are adjacent in
-    // the output
-    const uint32_t t = xcd_contiguous(blockIdx.x, nblocks);
-    if ((size_t)t * kTile >= n) return;  // whole block past the live count
-    __shared__ uint32_t s_k[kTile], s_v[kTile];
-    __shared__ uint32_t s_wc[kW][256];
-    __shared__ uint32_t s_bs[256], s_go[256], s_sw[kW];
+// Rank the keys of tile t inside the tile (wave ballots find equal digits,
+// lanes in order, waves in order: stable), reorder the tile in LDS and
+// write each digit run contiguously.
+struct ScatterLds {
+    uint32_t k[kTile], v[kTile];
+    uint32_t wc[kW][256];
+    uint32_t bs[256], go[256], sw[kW];
+};
+
+__device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n,
+                                             const uint32_t *kin, const uint32_t *vin,
+                                             uint32_t *kout, uint32_t *vout, int shift,
+                                             uint32_t bias, const uint32_t *hist,
+                                             uint32_t nblocks, int write_keys,
+                                             const uint32_t *tag) {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const size_t base = (size_t)t * kTile;
-    for (int d = tid; d < kW * 256; d += kT) (&s_wc[0][0])[d] = 0;
+    for (int d = tid; d < kW * 256; d += kT) (&L.wc[0][0])[d] = 0;
     // dg: the key's digit; entries past the live count take digit 255 so
     // that they rank after every live entry of the tile
     uint32_t k[kIpt], v[kIpt], r[kIpt], dg[kIpt];
@@ -263,9 +300,9 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
             m &= bit ? bal : ~bal;
         }
         const uint32_t rank = (uint32_t)__popcll(m & lt);
-        const uint32_t c = s_wc[w][d];
+        const uint32_t c = L.wc[w][d];
         r[j] = c + rank;
-        if (rank == 0) s_wc[w][d] = c + (uint32_t)__popcll(m);
+        if (rank == 0) L.wc[w][d] = c + (uint32_t)__popcll(m);
     }
     __syncthreads();
     uint32_t wpre[kW];
@@ -273,21 +310,21 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
 #pragma unroll
     for (int ww = 0; ww < kW; ++ww) {
         wpre[ww] = dtot;
-        dtot += s_wc[ww][tid];
+        dtot += L.wc[ww][tid];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_scan<kW>(dtot, s_sw, &tot);
-    s_bs[tid] = ex;
+    uint32_t ex = block_excl_scan<kW>(dtot, L.sw, &tot);
+    L.bs[tid] = ex;
 #pragma unroll
-    for (int ww = 0; ww < kW; ++ww) s_wc[ww][tid] = wpre[ww];
-    s_go[tid] = hist[(size_t)tid * nblocks + t];
+    for (int ww = 0; ww < kW; ++ww) L.wc[ww][tid] = wpre[ww];
+    L.go[tid] = hist[(size_t)tid * nblocks + t];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t d = dg[j];
-        const uint32_t pos = s_bs[d] + s_wc[w][d] + r[j];
-        s_k[pos] = k[j];
-        s_v[pos] = v[j];
+        const uint32_t pos = L.bs[d] + L.wc[w][d] + r[j];
+        L.k[pos] = k[j];
+        L.v[pos] = v[j];
     }
     __syncthreads();
     const size_t rem = n - base;
@@ -296,12 +333,38 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
     for (int q = 0; q < kIpt; ++q) {
         int p = q * kT + tid;
         if (p < nvalid) {
-            uint32_t key = s_k[p];
+            uint32_t key = L.k[p];
             uint32_t d = ((key - bias) >> shift) & 255u;
-            size_t g = (size_t)s_go[d] + (size_t)(p - (int)s_bs[d]);
+            size_t g = (size_t)L.go[d] + (size_t)(p - (int)L.bs[d]);
             if (write_keys) kout[g] = key;
-            vout[g] = s_v[p];
+            vout[g] = L.v[p];
         }
+    }
+}
+
+template <bool STRIDE>
+__global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
+                                                   uint32_t *kout, uint32_t *vout, size_t n_cap,
+                                                   const uint64_t *n_dev, int shift,
+                                                   uint32_t bias, const uint32_t *hist,
+                                                   uint32_t nblocks, int write_keys,
+                                                   const uint32_t *tag) {
+    const size_t n = live_count(n_cap, n_dev);
+    __shared__ ScatterLds L;
+    // the runs two neighbouring tiles write for one digit are adjacent in
+    // the output
+    if (!STRIDE) {
+        const uint32_t t = xcd_contiguous(blockIdx.x, nblocks);
+        if ((size_t)t * kTile < n)
+            scatter_tile(L, t, n, kin, vin, kout, vout, shift, bias, hist, nblocks, write_keys,
+                         tag);
+        return;
+    }
+    const PassTiles pt(n, nblocks);
+    for (uint32_t b = blockIdx.x; b < pt.live; b += gridDim.x) {
+        scatter_tile(L, pt.tile(b), n, kin, vin, kout, vout, shift, bias, hist, nblocks,
+                     write_keys, tag);
+        __syncthreads();  // before the next tile reuses the LDS
     }
 }
 
@@ -350,21 +413,32 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     void *scan_scratch =
         reinterpret_cast<char *>(scratch) + align_up((size_t)nb * 256 * sizeof(uint32_t), 256);
     const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+    // a count on the device: a capped grid of workgroups striding over the
+    // live tiles (a multiple of 8, so each keeps its XCD)
+    const uint32_t grid = n_dev ? std::min<uint32_t>(nb, kStrideGrid) : nb;
     int src = 0;
     for (int p = 0; p < passes; ++p) {
         uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
         uint32_t *kout = src ? k0 : k1, *vout = src ? v0 : v1;
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kT), 0, s, kin, n, n_dev, shift, bias, hist,
-                           nb);
+        if (n_dev)
+            hipLaunchKernelGGL(k_rs_hist<true>, dim3(grid), dim3(kT), 0, s, kin, n, n_dev, shift,
+                               bias, hist, nb);
+        else
+            hipLaunchKernelGGL(k_rs_hist<false>, dim3(grid), dim3(kT), 0, s, kin, n, n_dev, shift,
+                               bias, hist, nb);
         hipError_t e = launch_scan_u32(hist, (size_t)nb * 256, scan_scratch, s);
         if (e != hipSuccess) return e;
         const bool last = p == passes - 1;
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kT), 0, s, kin,
-                           (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin, kout,
-                           vout, n, n_dev, shift, bias, hist, nb,
-                           (!last || keys_needed) ? 1 : 0,
-                           (p == 0 && vals_identity) ? tag_counts : nullptr);
+        const uint32_t *vsrc = (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin;
+        const uint32_t *tag = (p == 0 && vals_identity) ? tag_counts : nullptr;
+        const int wk = (!last || keys_needed) ? 1 : 0;
+        if (n_dev)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(grid), dim3(kT), 0, s, kin, vsrc, kout,
+                               vout, n, n_dev, shift, bias, hist, nb, wk, tag);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(grid), dim3(kT), 0, s, kin, vsrc, kout,
+                               vout, n, n_dev, shift, bias, hist, nb, wk, tag);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         src ^= 1;

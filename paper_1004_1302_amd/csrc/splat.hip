@@ -106,14 +106,15 @@ __device__ __forceinline__ Col column(float d2, float r2, float qs) {
 // optical depth L crossed so far per channel (the transmittance is
 // exp(-L)) and, when the set has absorbers with E != A (GEN), the
 // transmittance D those absorbers removed and whether an E = A absorber
-// covered the pixel.
+// covered the pixel.  P: colour terms not yet added to C (see fold).
 struct Px {
-    float C0, C1, C2, K0, K1, K2, L0, L1, L2, D0, D1, D2, seen;
+    float C0, C1, C2, K0, K1, K2, L0, L1, L2, D0, D1, D2, seen, P0, P1, P2;
 };
 
 __device__ __forceinline__ void px_init(Px &p) {
     p.C0 = p.C1 = p.C2 = 0.f;
     p.K0 = p.K1 = p.K2 = 0.f;
+    p.P0 = p.P1 = p.P2 = 0.f;
     p.L0 = p.L1 = p.L2 = 0.f;
     p.D0 = p.D1 = p.D2 = 0.f;
     p.seen = 0.f;
@@ -151,24 +152,37 @@ __device__ __forceinline__ float trans_col(float L, Col c) {
 //     faint pixels exact to rounding: 1 - exp(-L) = -expm1(-L).
 //   Other absorbers: C += T e w phi(x), D += T x phi(x), L += x.
 // Additive (unordered) sets: C += e w.
-template <bool ORDERED, bool KAHAN, bool GEN>
+// A colour term s t (s, t its two factors) is added to C compensated, or,
+// with DEFER (compensated sums only), fused into the partial sum P, which
+// fold() adds to C compensated: a two-level compensated sum that costs
+// one fused multiply-add per term instead of five operations.
+template <bool KAHAN, bool DEFER>
+__device__ __forceinline__ void add_colour(float &C, float &K, float &P, float s, float t) {
+#pragma clang fp contract(off)
+    if (KAHAN && DEFER)
+        P = __builtin_fmaf(s, t, P);
+    else
+        add_term<false, KAHAN>(C, K, 1.f, s * t);
+}
+
+template <bool ORDERED, bool KAHAN, bool GEN, bool DEFER = false>
 __device__ __forceinline__ void composite(int kind, Col c, float e0, float e1, float e2, float a0,
                                           float a1, float a2, Px &p) {
 #pragma clang fp contract(off)
     if (!ORDERED) {
         const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
-        add_term<false, KAHAN>(p.C0, p.K0, 1.f, e0 * w);
-        add_term<false, KAHAN>(p.C1, p.K1, 1.f, e1 * w);
-        add_term<false, KAHAN>(p.C2, p.K2, 1.f, e2 * w);
+        add_colour<KAHAN, DEFER>(p.C0, p.K0, p.P0, e0, w);
+        add_colour<KAHAN, DEFER>(p.C1, p.K1, p.P1, e1, w);
+        add_colour<KAHAN, DEFER>(p.C2, p.K2, p.P2, e2, w);
     } else if (kind == kKindEmit) {
-        add_term<false, KAHAN>(p.C0, p.K0, 1.f, e0 * trans_col(p.L0, c));
-        add_term<false, KAHAN>(p.C1, p.K1, 1.f, e1 * trans_col(p.L1, c));
-        add_term<false, KAHAN>(p.C2, p.K2, 1.f, e2 * trans_col(p.L2, c));
+        add_colour<KAHAN, DEFER>(p.C0, p.K0, p.P0, e0, trans_col(p.L0, c));
+        add_colour<KAHAN, DEFER>(p.C1, p.K1, p.P1, e1, trans_col(p.L1, c));
+        add_colour<KAHAN, DEFER>(p.C2, p.K2, p.P2, e2, trans_col(p.L2, c));
     } else if (kind == kKindEqual) {
         const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
-        p.L0 += e0 * w;
-        p.L1 += e1 * w;
-        p.L2 += e2 * w;
+        p.L0 = __builtin_fmaf(e0, w, p.L0);
+        p.L1 = __builtin_fmaf(e1, w, p.L1);
+        p.L2 = __builtin_fmaf(e2, w, p.L2);
         if (GEN) p.seen = 1.f;
     } else {
         const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
@@ -178,9 +192,9 @@ __device__ __forceinline__ void composite(int kind, Col c, float e0, float e1, f
         const float t0 = __builtin_amdgcn_exp2f(-p.L0 * kLog2e);
         const float t1 = __builtin_amdgcn_exp2f(-p.L1 * kLog2e);
         const float t2 = __builtin_amdgcn_exp2f(-p.L2 * kLog2e);
-        add_term<false, KAHAN>(p.C0, p.K0, 1.f, t0 * ((e0 * w) * ph0));
-        add_term<false, KAHAN>(p.C1, p.K1, 1.f, t1 * ((e1 * w) * ph1));
-        add_term<false, KAHAN>(p.C2, p.K2, 1.f, t2 * ((e2 * w) * ph2));
+        add_colour<KAHAN, DEFER>(p.C0, p.K0, p.P0, t0, (e0 * w) * ph0);
+        add_colour<KAHAN, DEFER>(p.C1, p.K1, p.P1, t1, (e1 * w) * ph1);
+        add_colour<KAHAN, DEFER>(p.C2, p.K2, p.P2, t2, (e2 * w) * ph2);
         if (GEN) {
             p.D0 = __builtin_fmaf(t0, x0 * ph0, p.D0);
             p.D1 = __builtin_fmaf(t1, x1 * ph1, p.D1);
@@ -193,6 +207,17 @@ __device__ __forceinline__ void composite(int kind, Col c, float e0, float e1, f
         (void)ex1;
         (void)ex2;
     }
+}
+
+// Adds the partial sums P to C, compensated, and clears them.
+template <bool KAHAN>
+__device__ __forceinline__ void fold(Px &p) {
+#pragma clang fp contract(off)
+    if (!KAHAN) return;
+    kahan_step(p.C0, p.K0, p.P0 - p.K0);
+    kahan_step(p.C1, p.K1, p.P1 - p.K1);
+    kahan_step(p.C2, p.K2, p.P2 - p.K2);
+    p.P0 = p.P1 = p.P2 = 0.f;
 }
 
 // End of a pixel's list: adds the E = A absorbers' contribution,
@@ -381,6 +406,7 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
     const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
     if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
+    if (a.skip && *a.skip) return;
     const uint32_t tile = a.item_tile[item];
     if (a.tile_mask && !a.tile_mask[tile]) return;
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
@@ -520,6 +546,14 @@ __global__ __launch_bounds__(T *T) void k_splat_lists(SplatArgs a) {
 // the binary32 offset of the index recipe bit for bit.
 // One 8x8 block (sub) of one item: the body of the row walk, shared by the
 // per-view launch and the persistent multi-view launch.
+// Bits lo..hi of an 8-bit row or column mask (0 when the range misses
+// 0..7).
+__device__ __forceinline__ uint32_t span8(int lo, int hi) {
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > 7 ? 7 : hi;
+    return lo > hi ? 0u : (((2u << hi) - 1u) & ~((1u << lo) - 1u));
+}
+
 template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D, bool GEN>
 __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uint32_t sub) {
     constexpr int NT = T * T;
@@ -535,6 +569,7 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
 
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
     if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
+    if (a.skip && *a.skip) return;
     const uint32_t tile = a.item_tile[item];
     if (a.tile_mask && !a.tile_mask[tile]) return;
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
@@ -544,6 +579,8 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
     const int bx = tx0 + (int)(sub % QW) * 8, by = ty0 + (int)(sub / QW) * 8;
     const int i = bx + (lane & 7), j = by + (lane >> 3);
     const float tfx = (float)(2 * i + 1), tfy = (float)(2 * j + 1);
+    // this lane's column and row bits in a record's block box
+    const uint32_t sel = (1u << (lane & 7)) | (1u << (8 + (lane >> 3)));
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t seg_len = *a.seg_len;
     const uint32_t tend = a.tile_end[tile];
@@ -594,8 +631,11 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
     auto gather = [&](uint32_t n) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if ((uint32_t)lane < n) {
-            gidx = s_q[(head + lane) & (kQ - 1)];
+        if (n > 0) {
+            // lanes past the batch load its first record again: no lane
+            // keeps an old value, so nothing waits on the loads until the
+            // batch is expanded
+            gidx = s_q[(head + ((uint32_t)lane < n ? (uint32_t)lane : 0u)) & (kQ - 1)];
             ra = a.rec[gidx].a;
             rb = a.rec[gidx].b;
         }
@@ -605,16 +645,22 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
     uint32_t ncur = qn < kB ? qn : kB;
     gather(ncur);
     while (ncur > 0) {
+        uint32_t kflags = 0;
         if ((uint32_t)lane < ncur) {
             const Expanded x = expand_loaded(a, ra, rb, gidx, s_vmin, s_vmax);
             const int i0 = (int)(x.b0 & kBboxMask), i1 = (int)((x.b0 >> kBboxBits) & kBboxMask);
             const int j0 = (int)(x.b1 & kBboxMask), j1 = (int)((x.b1 >> kBboxBits) & kBboxMask);
+            // the block's columns and rows inside the record's box
+            const uint32_t box = span8(i0 - bx, i1 - bx) | (span8(j0 - by, j1 - by) << 8);
             s_r[0][lane] = make_float4(x.ur, x.vr, x.r2, x.qs);
-            s_r[1][lane] = make_float4((float)(2 * i0), (float)(2 * j0), (float)(2 * (i1 - i0) + 1),
-                                       (float)(2 * (j1 - j0) + 1));
-            s_r[2][lane] = make_float4(x.e[0], x.e[1], x.e[2], __uint_as_float(x.b1 & ~kRowMask));
+            s_r[1][lane] = make_float4((float)(2 * i0), (float)(2 * j0), __uint_as_float(box), 0.0f);
+            s_r[2][lane] = make_float4(x.e[0], x.e[1], x.e[2], 0.0f);
             s_r[3][lane] = make_float4(x.ab[0], x.ab[1], x.ab[2], 0.0f);
+            kflags = x.b1;
         }
+        // kinds of the staged records, one bit per record
+        const uint64_t m_emit = __ballot((kflags & kEmitOnly) != 0);
+        const uint64_t m_equal = __ballot((kflags & kEmitEqAbsorb) != 0);
         fill();
         const uint32_t nnext = qn < kB ? qn : kB;
         gather(nnext);
@@ -639,25 +685,28 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
                 const float dy = __builtin_fmaf(0.5f, ay, -f.y);
                 d2 = dx * dx + dy * dy;
             }
-            // no short-circuit: one mask, no branch around the comparisons
-            const bool in = (ax >= 1.0f) & (ax <= g.z) & (ay >= 1.0f) & (ay <= g.w) & (d2 <= f.z);
-            if (__ballot(in) == 0ull) return;
-            const uint32_t flags = __builtin_amdgcn_readfirstlane(__float_as_uint(e.w));
-            const bool emit_only = (flags & kEmitOnly) != 0;
+            // box: this lane's column and row bits both set; no
+            // short-circuit, so one mask and no branch around the tests
+            const bool in = ((__float_as_uint(g.z) & sel) == sel) & (d2 <= f.z);
+            // (a wave with no member lane skips the rest)
             if (!in) return;
+            const bool emit_only = ((m_emit >> r) & 1ull) != 0;
             if (COUNT) ++n_member;
             const Col cw = column<K3D>(d2, f.z, f.w);
             if (!ORDERED || emit_only) {
-                composite<ORDERED, KAHAN, GEN>(kKindEmit, cw, e.x, e.y, e.z, 0.f, 0.f, 0.f, px);
-            } else if (flags & kEmitEqAbsorb) {
-                if (COUNT) ++n_absorb;
+                composite<ORDERED, KAHAN, GEN, true>(kKindEmit, cw, e.x, e.y, e.z, 0.f, 0.f, 0.f,
+                                                     px);
+            } else if (!GEN || ((m_equal >> r) & 1ull)) {
+                // without absorbers of E != A every absorbing record is
                 // E = A: only the optical depth is carried
-                composite<ORDERED, KAHAN, GEN>(kKindEqual, cw, e.x, e.y, e.z, 0.f, 0.f, 0.f, px);
+                if (COUNT) ++n_absorb;
+                composite<ORDERED, KAHAN, GEN, true>(kKindEqual, cw, e.x, e.y, e.z, 0.f, 0.f,
+                                                     0.f, px);
             } else {
                 if (COUNT) ++n_absorb;
                 const float4 x = s_r[3][r];
-                composite<ORDERED, KAHAN, GEN>(kKindGeneral, cw, e.x, e.y, e.z, x.x, x.y, x.z,
-                                               px);
+                composite<ORDERED, KAHAN, GEN, true>(kKindGeneral, cw, e.x, e.y, e.z, x.x, x.y,
+                                                     x.z, px);
             }
         };
         // four visits per trip: the register allocator rotates the running
@@ -671,6 +720,8 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
             visit(r + 3);
         }
         for (; r < ncur; ++r) visit(r);
+        // the batch's colour terms into the compensated sum
+        fold<KAHAN>(px);
         // before the next batch overwrites the rows
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -726,12 +777,17 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
 }
 
 // Persistent row walk over the items of several views at once: the views'
-// settings sit in device memory, their item counts are read on the device,
-// and each workgroup takes units (item, 8x8 block) of the concatenated item
-// sequence in the same XCD-aware order as the per-view launch until none
-// is left.
+// settings sit in device memory and their item counts are read on the
+// device.  Units (item, 8x8 block) of the concatenated item sequence are
+// handed out dynamically, one counter per XCD: a workgroup on XCD x (the
+// hardware deals workgroups to the 8 XCDs round-robin) takes that XCD's
+// next unit of the per-view launch's order, so units keep their XCD and
+// a tile's blocks still share one L2, while long and short units balance
+// as they would under the hardware's own dispatch.  Units past the last
+// item end the loop: their run base only grows with the counter.
 template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D, bool GEN>
-__global__ __launch_bounds__(64) void k_splat_rows_multi(const SplatArgs *views, int nv) {
+__global__ __launch_bounds__(64) void k_splat_rows_multi(const SplatArgs *views, int nv,
+                                                         uint32_t *next) {
     uint32_t first[kMaxGroup + 1];
     first[0] = 0;
     for (int v = 0; v < kMaxGroup; ++v) {
@@ -744,9 +800,13 @@ __global__ __launch_bounds__(64) void k_splat_rows_multi(const SplatArgs *views,
         first[v + 1] = first[v] + n;
     }
     const uint32_t total = first[nv];
-    for (uint32_t b = blockIdx.x;; b += gridDim.x) {
+    const uint32_t x = blockIdx.x & 7u;
+    for (;;) {
+        uint32_t k = 0;
+        if (threadIdx.x == 0) k = atomicAdd(&next[x], 1u);
+        k = (uint32_t)__shfl((int)k, 0, 64);
         uint32_t item, sub, base;
-        unit_of<T>(b, &item, &sub, &base);
+        unit_of<T>(8u * k + x, &item, &sub, &base);
         if (base >= total) break;
         if (item >= total) continue;
         int v = 0;
@@ -794,6 +854,7 @@ __global__ __launch_bounds__(64) void k_splat_box(SplatArgs a) {
     const uint32_t item = (k / kRun) * (8 * kRun) + (b & 7) * kRun + (k % kRun);
     const uint32_t ntiles = (uint32_t)(a.ntx * a.nty);
     if (item >= a.seg_off[ntiles] || item >= a.max_items) return;
+    if (a.skip && *a.skip) return;
     const uint32_t tile = a.item_tile[item];
     if (a.tile_mask && !a.tile_mask[tile]) return;
     const uint32_t seg = item - (uint32_t)a.seg_off[tile];
@@ -983,6 +1044,7 @@ __global__ __launch_bounds__(T *T < 1024 ? T *T : 1024) void k_merge(SplatArgs a
     const uint32_t tile = blockIdx.x;
     const uint32_t nseg = (uint32_t)(a.seg_off[tile + 1] - a.seg_off[tile]);
     if (nseg <= 1 || (a.tile_mask && !a.tile_mask[tile])) return;
+    if (a.skip && *a.skip) return;
     if (a.part_off[tile] + nseg > a.max_slots) return;  // never: the slot bound holds
     const int tx = (int)(tile % (uint32_t)a.ntx), ty = (int)(tile / (uint32_t)a.ntx);
     for (int p = threadIdx.x; p < NT; p += blockDim.x) {
@@ -1092,38 +1154,42 @@ __global__ void k_store_args(SplatArgs a, SplatArgs *dst) {
 }
 
 template <int T, bool ORDERED, bool KAHAN, bool GEN>
-hipError_t launch_multi_tok(const SplatArgs *views, int nv, const SplatArgs &a, hipStream_t s) {
+hipError_t launch_multi_tok(const SplatArgs *views, int nv, const SplatArgs &a, uint32_t *next,
+                            hipStream_t s) {
     // a persistent grid: 8 single-wave workgroups per SIMD, a multiple of 8
     const dim3 g(256 * 4 * 8), b(64);
+    hipError_t e = launch_fill_u32(next, 0u, kUnitCounters, s);
+    if (e != hipSuccess) return e;
     if (a.kernel3d) {
         if (a.count)
             hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, true, true, GEN>), g, b, 0, s,
-                               views, nv);
+                               views, nv, next);
         else
             hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, false, true, GEN>), g, b, 0,
-                               s, views, nv);
+                               s, views, nv, next);
     } else {
         if (a.count)
             hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, true, false, GEN>), g, b, 0,
-                               s, views, nv);
+                               s, views, nv, next);
         else
             hipLaunchKernelGGL((k_splat_rows_multi<T, ORDERED, KAHAN, false, false, GEN>), g, b, 0,
-                               s, views, nv);
+                               s, views, nv, next);
     }
     return hipGetLastError();
 }
 
 template <int T>
-hipError_t launch_multi_t(const SplatArgs *views, int nv, const SplatArgs &a, hipStream_t s) {
+hipError_t launch_multi_t(const SplatArgs *views, int nv, const SplatArgs &a, uint32_t *next,
+                          hipStream_t s) {
     if (a.ordered) {
         if (a.general)
-            return a.compensated ? launch_multi_tok<T, true, true, true>(views, nv, a, s)
-                                 : launch_multi_tok<T, true, false, true>(views, nv, a, s);
-        return a.compensated ? launch_multi_tok<T, true, true, false>(views, nv, a, s)
-                             : launch_multi_tok<T, true, false, false>(views, nv, a, s);
+            return a.compensated ? launch_multi_tok<T, true, true, true>(views, nv, a, next, s)
+                                 : launch_multi_tok<T, true, false, true>(views, nv, a, next, s);
+        return a.compensated ? launch_multi_tok<T, true, true, false>(views, nv, a, next, s)
+                             : launch_multi_tok<T, true, false, false>(views, nv, a, next, s);
     }
-    return a.compensated ? launch_multi_tok<T, false, true, false>(views, nv, a, s)
-                         : launch_multi_tok<T, false, false, false>(views, nv, a, s);
+    return a.compensated ? launch_multi_tok<T, false, true, false>(views, nv, a, next, s)
+                         : launch_multi_tok<T, false, false, false>(views, nv, a, next, s);
 }
 
 template <int T>
@@ -1151,13 +1217,13 @@ hipError_t store_splat_args(const SplatArgs &a, SplatArgs *dst, hipStream_t s) {
 }
 
 hipError_t launch_splat_multi(const SplatArgs *views, int nv, const SplatArgs &a,
-                              hipStream_t s) {
+                              uint32_t *next, hipStream_t s) {
     if (nv < 1 || nv > kMaxGroup || a.variant != kSplatRows) return hipErrorInvalidValue;
     switch (a.tile) {
-        case 8: return launch_multi_t<8>(views, nv, a, s);
-        case 16: return launch_multi_t<16>(views, nv, a, s);
-        case 32: return launch_multi_t<32>(views, nv, a, s);
-        case 64: return launch_multi_t<64>(views, nv, a, s);
+        case 8: return launch_multi_t<8>(views, nv, a, next, s);
+        case 16: return launch_multi_t<16>(views, nv, a, next, s);
+        case 32: return launch_multi_t<32>(views, nv, a, next, s);
+        case 64: return launch_multi_t<64>(views, nv, a, next, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -239,8 +239,10 @@ Acts layout_acts(splotch_nn *net, int n, int h, int w) {
 
 bool valid_shape(const splotch_nn *net, int n, int h, int w) {
     const int m = 1 << (net->cfg.n_levels - 1);
+    // the pixel count is a GEMM dimension (int); every buffer offset is
+    // 64-bit
     return n >= 1 && h >= 1 && w >= 1 && h % m == 0 && w % m == 0 &&
-           (uint64_t)n * h * w * 9 * 256 < (1ull << 31);
+           (uint64_t)n * h * w < (1ull << 31);
 }
 
 Acts &acts(splotch_nn *net, int n, int h, int w) {

@@ -154,14 +154,31 @@ def test_graph_replays_track_eager(scene):
     assert B.graph_cache_clear() == 1
 
 
-def test_batch_overflow_is_flagged(scene):
+def test_batch_overflow_is_chunked(scene):
+    """A view whose pairs exceed the capacity of its part of the workspace
+    writes nothing in the batch; an eager batch then renders it in
+    workspace-bounded chunks, the same bits as a single render with that
+    capacity.  A graph replay cannot branch on the flag: it reports the
+    view (SPLOTCH_E_CAPACITY with stats) and leaves its image untouched."""
     import torch
     parts, pal = B.scene_to_device(scene)
     cams = orbit_cameras(3, 3, [(128, 128)])
+    kw = dict(max_pairs=20_000, compensated=True)
+    imgs, st = B.render_batch(parts, cams, pal, scene.species_params, stats=True, **kw)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(cams):
+        ref, one = B.render(parts, cam, pal, scene.species_params, stats=True, **kw)
+        torch.cuda.synchronize()
+        assert one["n_chunks"] > 1 and st[v]["n_chunks"] == one["n_chunks"]
+        assert np.array_equal(imgs[v].cpu().numpy(), ref.cpu().numpy()), v
+    for im in imgs:
+        im.fill_(-1.0)
     with pytest.raises(B.SplotchError) as e:
-        B.render_batch(parts, cams, pal, scene.species_params, max_pairs=20_000, stats=True)
+        B.render_batch(parts, cams, pal, scene.species_params, imgs, stats=True, graph=True, **kw)
     assert e.value.code == 5
     torch.cuda.synchronize()
+    assert all(bool((im == -1.0).all()) for im in imgs)
+    B.graph_cache_clear()
     # the library is still usable afterwards
     imgs = B.render_batch(parts, cams, pal, scene.species_params, compensated=True)
     torch.cuda.synchronize()

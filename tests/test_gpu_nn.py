@@ -352,6 +352,27 @@ def test_training_gains_over_decimated_render(torch):
     assert np.mean(gains) > 1.0
 
 
+def test_training_step_at_full_size(torch):
+    """One training step at the learned path's shape (4 images of 1024^2,
+    the largest activations: 4 Mpx x 9 taps x 64 channels in the
+    backward GEMMs) and one reconstruction: finite loss and output.
+    Shapes of 2^31 pixels or more are refused on the host."""
+    net = LN.UNet(seed=3)
+    rec = LN.Reconstructor(net)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    full = [torch.rand((3, 1024, 1024), device="cuda", generator=g) for _ in range(4)]
+    dec = [f * torch.rand((3, 1024, 1024), device="cuda", generator=g) for f in full]
+    part = rec.train_step(dec, full, lr=1e-3)
+    out = rec.infer(dec[0])
+    torch.cuda.synchronize()
+    assert math.isfinite(float(part.sum())) and float(part.sum()) > 0
+    assert bool(torch.isfinite(out).all())
+    import ctypes as C
+    nb = C.c_size_t(0)
+    assert net.L.splotch_nn_workspace_bytes(net.h, 4, 1024, 1024, C.byref(nb)) == 0
+    assert net.L.splotch_nn_workspace_bytes(net.h, 2048, 1024, 1024, C.byref(nb)) == 1
+
+
 def test_probe_and_fallback(torch):
     """Threshold 0 dB never falls back; an unreachable threshold always does
     and then returns exactly the full render.  The device PSNR of the probe
