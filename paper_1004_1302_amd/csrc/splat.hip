@@ -165,9 +165,12 @@ __device__ __forceinline__ void add_colour(float &C, float &K, float &P, float s
         add_term<false, KAHAN>(C, K, 1.f, s * t);
 }
 
+// member: false for a lane that runs the arithmetic without being covered
+// (its column is 2^-inf = 0, so every term is an exact zero); it then only
+// keeps `seen` as it was.
 template <bool ORDERED, bool KAHAN, bool GEN, bool DEFER = false>
 __device__ __forceinline__ void composite(int kind, Col c, float e0, float e1, float e2, float a0,
-                                          float a1, float a2, Px &p) {
+                                          float a1, float a2, Px &p, bool member = true) {
 #pragma clang fp contract(off)
     if (!ORDERED) {
         const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
@@ -183,7 +186,7 @@ __device__ __forceinline__ void composite(int kind, Col c, float e0, float e1, f
         p.L0 = __builtin_fmaf(e0, w, p.L0);
         p.L1 = __builtin_fmaf(e1, w, p.L1);
         p.L2 = __builtin_fmaf(e2, w, p.L2);
-        if (GEN) p.seen = 1.f;
+        if (GEN) p.seen = member ? 1.f : p.seen;
     } else {
         const float w = __builtin_amdgcn_exp2f(-c.q) * c.g;
         const float x0 = a0 * w, x1 = a1 * w, x2 = a2 * w;
@@ -364,6 +367,12 @@ __device__ __forceinline__ Expanded expand_loaded(const SplatArgs &a, uint4 ra, 
         x.e[0] *= a0 * ar;
         x.e[1] *= a0 * ag;
         x.e[2] *= a0 * abb;
+    }
+    // finite colours (an overflow saturates): the row walk multiplies them
+    // by an exact zero on pixels a record does not cover
+    for (int c = 0; c < 3; ++c) {
+        x.e[c] = fminf(x.e[c], 3.40282347e38f);
+        x.ab[c] = fminf(x.ab[c], 3.40282347e38f);
     }
     const bool same = x.e[0] == x.ab[0] && x.e[1] == x.ab[1] && x.e[2] == x.ab[2];
     x.b1 = (ra.y & 0x0FFFFFFFu) | ((ab == 0.0f) ? kEmitOnly : 0u) |
@@ -688,25 +697,31 @@ __device__ __forceinline__ void rows_unit(const SplatArgs &a, uint32_t item, uin
             // box: this lane's column and row bits both set; no
             // short-circuit, so one mask and no branch around the tests
             const bool in = ((__float_as_uint(g.z) & sel) == sel) & (d2 <= f.z);
-            // (a wave with no member lane skips the rest)
-            if (!in) return;
-            const bool emit_only = ((m_emit >> r) & 1ull) != 0;
-            if (COUNT) ++n_member;
-            const Col cw = column<K3D>(d2, f.z, f.w);
-            if (!ORDERED || emit_only) {
+            // a wave with no member lane skips the rest
+            if (__builtin_amdgcn_ballot_w64(in) == 0ull) return;
+            // Every lane runs the member arithmetic: a vector instruction
+            // with at most 8 active lanes issues at about a fifth of the
+            // full rate, and no branch means no copies at a join.  A
+            // non-member's column is 2^-inf = 0, so its terms are exact
+            // zeros.
+            Col cw = column<K3D>(d2, f.z, f.w);
+            cw.q = in ? cw.q : __builtin_inff();
+            const uint32_t one = in ? 1u : 0u;
+            if (COUNT) n_member += one;
+            if (!ORDERED || ((m_emit >> r) & 1ull)) {
                 composite<ORDERED, KAHAN, GEN, true>(kKindEmit, cw, e.x, e.y, e.z, 0.f, 0.f, 0.f,
-                                                     px);
+                                                     px, in);
             } else if (!GEN || ((m_equal >> r) & 1ull)) {
                 // without absorbers of E != A every absorbing record is
                 // E = A: only the optical depth is carried
-                if (COUNT) ++n_absorb;
+                if (COUNT) n_absorb += one;
                 composite<ORDERED, KAHAN, GEN, true>(kKindEqual, cw, e.x, e.y, e.z, 0.f, 0.f,
-                                                     0.f, px);
+                                                     0.f, px, in);
             } else {
-                if (COUNT) ++n_absorb;
+                if (COUNT) n_absorb += one;
                 const float4 x = s_r[3][r];
                 composite<ORDERED, KAHAN, GEN, true>(kKindGeneral, cw, e.x, e.y, e.z, x.x, x.y,
-                                                     x.z, px);
+                                                     x.z, px, in);
             }
         };
         // four visits per trip: the register allocator rotates the running

@@ -48,6 +48,20 @@ def check_image(gpu, ref, tol=TOL):
     return rel
 
 
+def check_pixels(gpu, ref, rel=1e-4, floor=1e-6):
+    """Per-pixel bound for compensated renders: every pixel within rel of
+    its own oracle value, plus an absolute floor of `floor` times the
+    channel's largest oracle value (pixels that faint are at the level of
+    the FP32 resolution of the bright ones).  Arrays are [3][...] or
+    [..., 3] with channel_axis 0."""
+    g = gpu.astype(np.float64).reshape(3, -1)
+    o = np.asarray(ref, np.float64).reshape(3, -1)
+    bound = rel * np.abs(o) + floor * np.abs(o).max(axis=1, keepdims=True)
+    worst = (np.abs(g - o) / np.where(bound > 0, bound, 1.0)).max(axis=1)
+    assert np.all(np.abs(g - o) <= bound), f"per-pixel error over the bound: {worst}"
+    return worst
+
+
 def expected_bins(pr, scene, tile, ordered):
     W, H = scene.camera.width, scene.camera.height
     ntx, nty = -(-W // tile), -(-H // tile)
@@ -184,6 +198,8 @@ def test_c1_full_additive(torch_cuda, orc, tile, compensated):
     ref = orc.render(scene)
     img, st = gpu_render(scene, tile=tile, compensated=compensated, stats=True)
     check_image(img, ref)
+    if compensated:
+        check_pixels(img, ref)
     assert st["ordered"] == 0 and st["n_chunks"] == 1
 
 
@@ -196,6 +212,8 @@ def test_c2_small_mixed_ordered(torch_cuda, orc, compensated, variant):
     ref = orc.render(scene)
     img, st = gpu_render(scene, compensated=compensated, stats=True, splat_variant=variant)
     check_image(img, ref)
+    if compensated:
+        check_pixels(img, ref)
     assert st["ordered"] == 1
 
 
