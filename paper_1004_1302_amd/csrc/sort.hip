@@ -220,34 +220,38 @@ constexpr int kHistCopies = 16;
 
 // STRIDE: the grid strides over the tiles (a count on the device); else one
 // workgroup per tile.
-template <bool STRIDE>
+// DB: digit bits (7 or 8): the histogram has 2^DB columns per tile.
+template <bool STRIDE, int DB>
 __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_cap,
                                                 const uint64_t *n_dev, int shift, uint32_t bias,
                                                 uint32_t *hist, uint32_t nblocks) {
+    constexpr uint32_t ND = 1u << DB, DM = ND - 1u;
     const size_t n = live_count(n_cap, n_dev);
     const PassTiles pt(n, nblocks);
-    __shared__ uint32_t sh[kHistCopies][256];
+    __shared__ uint32_t sh[kHistCopies][ND];
     const int c = threadIdx.x & (kHistCopies - 1);
     for (uint32_t b = blockIdx.x; b < pt.all; b += STRIDE ? gridDim.x : pt.all) {
         // neighbouring tiles' counts share lines of the digit-major histogram
         const uint32_t t = pt.tile(b);
         if (b >= pt.live) {
-            hist[(size_t)threadIdx.x * nblocks + t] = 0u;
+            if (threadIdx.x < ND) hist[(size_t)threadIdx.x * nblocks + t] = 0u;
             continue;
         }
-        for (int d = threadIdx.x; d < kHistCopies * 256; d += kT) (&sh[0][0])[d] = 0;
+        for (int d = threadIdx.x; d < kHistCopies * (int)ND; d += kT) (&sh[0][0])[d] = 0;
         __syncthreads();
         const size_t base = (size_t)t * kTile;
 #pragma unroll
         for (int q = 0; q < kIpt; ++q) {
             size_t idx = base + (size_t)q * kT + threadIdx.x;
-            if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & 255u], 1u);
+            if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & DM], 1u);
         }
         __syncthreads();
-        uint32_t sum = 0;
+        if (threadIdx.x < ND) {
+            uint32_t sum = 0;
 #pragma unroll
-        for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
-        hist[(size_t)threadIdx.x * nblocks + t] = sum;
+            for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
+            hist[(size_t)threadIdx.x * nblocks + t] = sum;
+        }
         if (!STRIDE) break;
         __syncthreads();  // before the next tile clears the counters
     }
@@ -256,21 +260,24 @@ __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_c
 // Rank the keys of tile t inside the tile (wave ballots find equal digits,
 // lanes in order, waves in order: stable), reorder the tile in LDS and
 // write each digit run contiguously.
+template <int DB>
 struct ScatterLds {
     uint32_t k[kTile], v[kTile];
-    uint32_t wc[kW][256];
-    uint32_t bs[256], go[256], sw[kW];
+    uint32_t wc[kW][1 << DB];
+    uint32_t bs[1 << DB], go[1 << DB], sw[kW];
 };
 
-__device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n,
+template <int DB>
+__device__ __forceinline__ void scatter_tile(ScatterLds<DB> &L, uint32_t t, size_t n,
                                              const uint32_t *kin, const uint32_t *vin,
                                              uint32_t *kout, uint32_t *vout, int shift,
                                              uint32_t bias, const uint32_t *hist,
                                              uint32_t nblocks, int write_keys,
                                              const uint32_t *tag) {
+    constexpr uint32_t ND = 1u << DB, DM = ND - 1u;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const size_t base = (size_t)t * kTile;
-    for (int d = tid; d < kW * 256; d += kT) (&L.wc[0][0])[d] = 0;
+    for (int d = tid; d < kW * (int)ND; d += kT) (&L.wc[0][0])[d] = 0;
     // dg: the key's digit; entries past the live count take digit 255 so
     // that they rank after every live entry of the tile
     uint32_t k[kIpt], v[kIpt], r[kIpt], dg[kIpt];
@@ -280,11 +287,11 @@ __device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n
         if (idx < n) {
             k[j] = kin[idx];
             v[j] = vin ? vin[idx] : (tag ? tag_value((uint32_t)idx, tag[idx]) : (uint32_t)idx);
-            dg[j] = ((k[j] - bias) >> shift) & 255u;
+            dg[j] = ((k[j] - bias) >> shift) & DM;
         } else {
             k[j] = 0xFFFFFFFFu;
             v[j] = 0u;
-            dg[j] = 255u;
+            dg[j] = DM;
         }
     }
     __syncthreads();
@@ -294,7 +301,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n
         const uint32_t d = dg[j];
         uint64_t m = ~0ull;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < DB; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t bal = __ballot(bit);
             m &= bit ? bal : ~bal;
@@ -305,19 +312,24 @@ __device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n
         if (rank == 0) L.wc[w][d] = c + (uint32_t)__popcll(m);
     }
     __syncthreads();
+    // one thread per digit; the others add nothing to the scan
+    const int dd = tid & (int)DM;
     uint32_t wpre[kW];
     uint32_t dtot = 0;
 #pragma unroll
     for (int ww = 0; ww < kW; ++ww) {
         wpre[ww] = dtot;
-        dtot += L.wc[ww][tid];
+        dtot += L.wc[ww][dd];
     }
+    if (tid >= (int)ND) dtot = 0;
     uint32_t tot;
     uint32_t ex = block_excl_scan<kW>(dtot, L.sw, &tot);
-    L.bs[tid] = ex;
+    if (tid < (int)ND) {
+        L.bs[tid] = ex;
 #pragma unroll
-    for (int ww = 0; ww < kW; ++ww) L.wc[ww][tid] = wpre[ww];
-    L.go[tid] = hist[(size_t)tid * nblocks + t];
+        for (int ww = 0; ww < kW; ++ww) L.wc[ww][tid] = wpre[ww];
+        L.go[tid] = hist[(size_t)tid * nblocks + t];
+    }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
@@ -334,7 +346,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n
         int p = q * kT + tid;
         if (p < nvalid) {
             uint32_t key = L.k[p];
-            uint32_t d = ((key - bias) >> shift) & 255u;
+            uint32_t d = ((key - bias) >> shift) & DM;
             size_t g = (size_t)L.go[d] + (size_t)(p - (int)L.bs[d]);
             if (write_keys) kout[g] = key;
             vout[g] = L.v[p];
@@ -342,7 +354,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds &L, uint32_t t, size_t n
     }
 }
 
-template <bool STRIDE>
+template <bool STRIDE, int DB>
 __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
                                                    uint32_t *kout, uint32_t *vout, size_t n_cap,
                                                    const uint64_t *n_dev, int shift,
@@ -350,7 +362,7 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
                                                    uint32_t nblocks, int write_keys,
                                                    const uint32_t *tag) {
     const size_t n = live_count(n_cap, n_dev);
-    __shared__ ScatterLds L;
+    __shared__ ScatterLds<DB> L;
     // the runs two neighbouring tiles write for one digit are adjacent in
     // the output
     if (!STRIDE) {
@@ -402,6 +414,29 @@ size_t radix_scratch_bytes(size_t n) {
     return hist + scan_u32_scratch_bytes(nb * 256);
 }
 
+// One pass: digit histogram per tile, its scan, the scatter.
+template <int DB>
+hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+                      size_t n, const uint64_t *n_dev, int shift, uint32_t bias, uint32_t *hist,
+                      uint32_t nb, int write_keys, const uint32_t *tag, uint32_t grid,
+                      void *scan_scratch, hipStream_t s) {
+    if (n_dev)
+        hipLaunchKernelGGL((k_rs_hist<true, DB>), dim3(grid), dim3(kT), 0, s, kin, n, n_dev,
+                           shift, bias, hist, nb);
+    else
+        hipLaunchKernelGGL((k_rs_hist<false, DB>), dim3(grid), dim3(kT), 0, s, kin, n, n_dev,
+                           shift, bias, hist, nb);
+    hipError_t e = launch_scan_u32(hist, (size_t)nb << DB, scan_scratch, s);
+    if (e != hipSuccess) return e;
+    if (n_dev)
+        hipLaunchKernelGGL((k_rs_scatter<true, DB>), dim3(grid), dim3(kT), 0, s, kin, vin, kout,
+                           vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
+    else
+        hipLaunchKernelGGL((k_rs_scatter<false, DB>), dim3(grid), dim3(kT), 0, s, kin, vin, kout,
+                           vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
+    return hipGetLastError();
+}
+
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
                             uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
@@ -413,6 +448,9 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     void *scan_scratch =
         reinterpret_cast<char *>(scratch) + align_up((size_t)nb * 256 * sizeof(uint32_t), 256);
     const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
+    // 7-bit digits when they cover the key in as many passes: half the
+    // histogram, and digit runs twice as long in the scatter's writes
+    const int db = bits > 0 && bits <= 7 * passes ? 7 : 8;
     // a count on the device: a capped grid of workgroups striding over the
     // live tiles (a multiple of 8, so each keeps its XCD)
     const uint32_t grid = n_dev ? std::min<uint32_t>(nb, kStrideGrid) : nb;
@@ -420,26 +458,15 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     for (int p = 0; p < passes; ++p) {
         uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
         uint32_t *kout = src ? k0 : k1, *vout = src ? v0 : v1;
-        const int shift = 8 * p;
-        if (n_dev)
-            hipLaunchKernelGGL(k_rs_hist<true>, dim3(grid), dim3(kT), 0, s, kin, n, n_dev, shift,
-                               bias, hist, nb);
-        else
-            hipLaunchKernelGGL(k_rs_hist<false>, dim3(grid), dim3(kT), 0, s, kin, n, n_dev, shift,
-                               bias, hist, nb);
-        hipError_t e = launch_scan_u32(hist, (size_t)nb * 256, scan_scratch, s);
-        if (e != hipSuccess) return e;
+        const int shift = db * p;
         const bool last = p == passes - 1;
         const uint32_t *vsrc = (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin;
         const uint32_t *tag = (p == 0 && vals_identity) ? tag_counts : nullptr;
         const int wk = (!last || keys_needed) ? 1 : 0;
-        if (n_dev)
-            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(grid), dim3(kT), 0, s, kin, vsrc, kout,
-                               vout, n, n_dev, shift, bias, hist, nb, wk, tag);
-        else
-            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(grid), dim3(kT), 0, s, kin, vsrc, kout,
-                               vout, n, n_dev, shift, bias, hist, nb, wk, tag);
-        e = hipGetLastError();
+        hipError_t e = db == 7 ? radix_pass<7>(kin, vsrc, kout, vout, n, n_dev, shift, bias, hist,
+                                               nb, wk, tag, grid, scan_scratch, s)
+                               : radix_pass<8>(kin, vsrc, kout, vout, n, n_dev, shift, bias, hist,
+                                               nb, wk, tag, grid, scan_scratch, s);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
