@@ -587,9 +587,14 @@ def learned_leg(args, np, torch):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
 
+    from scipy.ndimage import gaussian_filter
+    blur_sigmas = (0.5, 1.0, 2.0)
+
     def evaluate(pset, views):
         parts, dec = pset[:2]
         psnr_net, psnr_dec, maxerr, fb = [], [], [], 0
+        lin_net, lin_dec = [], []
+        psnr_blur = {sg: [] for sg in blur_sigmas}
         ev = lambda: torch.cuda.Event(enable_timing=True)
         t_learn, t_full = [], []
         for c in views:
@@ -608,6 +613,12 @@ def learned_leg(args, np, torch):
             fh, oh, dh = full.cpu().numpy(), out.cpu().numpy(), d.cpu().numpy()
             psnr_net.append(LN.psnr_tonemapped(oh, fh))
             psnr_dec.append(LN.psnr_tonemapped(dh, fh))
+            lin_net.append(LN.psnr_linear(oh, fh))
+            lin_dec.append(LN.psnr_linear(dh, fh))
+            # a non-learned baseline: the decimated render blurred by a
+            # Gaussian of sigma px
+            for sg in blur_sigmas:
+                psnr_blur[sg].append(LN.psnr_tonemapped(gaussian_filter(dh, (0, sg, sg)), fh))
             maxerr.append(float(np.abs(oh - fh).max() / max(np.abs(fh).max(), 1e-30)))
             fb += int(info["fallback"])
         med = lambda a: float(np.median(a))
@@ -615,6 +626,13 @@ def learned_leg(args, np, torch):
             "psnr_net_median_db": round(med(psnr_net), 3),
             "psnr_decimated_median_db": round(med(psnr_dec), 3),
             "psnr_gain_median_db": round(med(np.array(psnr_net) - np.array(psnr_dec)), 3),
+            "psnr_blurred_decimated_median_db": {str(sg): round(med(v), 3)
+                                                 for sg, v in psnr_blur.items()},
+            "psnr_gain_over_best_blur_median_db": round(
+                med(np.array(psnr_net) - np.max([psnr_blur[sg] for sg in blur_sigmas], axis=0)),
+                3),
+            "psnr_linear_net_median_db": round(med(lin_net), 3),
+            "psnr_linear_decimated_median_db": round(med(lin_dec), 3),
             "max_rel_error_median": round(med(maxerr), 5),
             "fallback_rate_at_40db": fb / len(views),
             "ms_full_render_median": round(med(t_full), 3),

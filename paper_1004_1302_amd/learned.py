@@ -390,6 +390,18 @@ def psnr_tonemapped(img, ref):
     return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
 
 
+def psnr_linear(img, ref):
+    """PSNR of img against ref with the reference's largest value as the
+    peak (host numpy arrays [3,H,W])."""
+    ref = np.asarray(ref, np.float64)
+    img = np.asarray(img, np.float64)
+    peak = float(np.abs(ref).max())
+    mse = float(((img - ref) ** 2).mean())
+    if mse == 0:
+        return float("inf")
+    return float("-inf") if peak == 0 else 10.0 * math.log10(peak * peak / mse)
+
+
 def probe_mask(width, height, tile, frac, seed, device):
     """splotch_probe_mask: a seeded sample of about frac of the screen tiles
     (at least one), as a device uint8 mask and its host copy [nty, ntx]."""
