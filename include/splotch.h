@@ -249,8 +249,10 @@ typedef struct splotch_image {
     int32_t width, height;
 } splotch_image;
 
-/* Human-readable name of a status code (static string, never NULL). */
-const char *splotch_status_string(splotch_status s);
+/* Human-readable name of a status code (static string, never NULL).  The
+ * argument is a plain integer so that any value a caller holds is valid;
+ * one that names no splotch_status gives "unknown status". */
+const char *splotch_status_string(int32_t code);
 
 /* Fill *cam with a camera at eye looking at `at` with the given up hint
  * (host arrays of 3).  projection PERSPECTIVE: fov_or_scale is the

@@ -840,8 +840,8 @@ splotch_status enqueue_batch(std::vector<Ctx> &lanes, const LaneSet *ls,
 
 extern "C" {
 
-const char *splotch_status_string(splotch_status s) {
-    switch (s) {
+const char *splotch_status_string(int32_t code) {
+    switch (code) {
         case SPLOTCH_OK: return "ok";
         case SPLOTCH_E_INVALID_ARG: return "invalid argument";
         case SPLOTCH_E_WORKSPACE: return "workspace missing, misaligned or too small";
