@@ -13,6 +13,7 @@ SOURCES = ["api.hip", "project.hip", "sort.hip", "bin.hip", "splat.hip", "nn.hip
            "learned.hip", "stream.hip", "render_static.hip"]
 ARCH = os.environ.get("SPLOTCH_OFFLOAD_ARCH", "gfx950")
 
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
@@ -64,7 +65,9 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    # trace ranges and markers (roctx) for rocprofv3 --marker-trace
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{ROCM}/lib", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM}/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
@@ -107,7 +110,8 @@ def build_host_sanitized() -> str:
     if failed:
         raise RuntimeError(f"hipcc (sanitized host build) failed for {failed}")
     tmp = SAN_LIB + ".tmp"
-    subprocess.check_call([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    subprocess.check_call([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+                           f"-L{ROCM}/lib", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM}/lib"])
     os.replace(tmp, SAN_LIB)
     with open(stamp, "w") as f:
         f.write(digest)

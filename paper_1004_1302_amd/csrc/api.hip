@@ -283,7 +283,12 @@ void splat_colour_args(SplatArgs *sa, const splotch_particles *P, const splotch_
         if ((expr) != hipSuccess) return SPLOTCH_E_DEVICE; \
     } while (0)
 
-// Stage timer: HIP events recorded on the render's stream between stages.
+// Names of the stages in the timer and in the trace markers.
+const char *const kStageName[] = {"splotch: project", "splotch: depth sort", "splotch: scan",
+                                  "splotch: emit", "splotch: tile sort", "splotch: splat"};
+
+// Stage timer: HIP events recorded on the render's stream between stages,
+// and a trace marker at the end of each stage's launches.
 struct Prof {
     bool on = false;
     hipStream_t s = nullptr;
@@ -296,6 +301,7 @@ struct Prof {
         return mark(-1);
     }
     hipError_t mark(int stg) {
+        if (stg >= 0 && stg < 6) roctxMarkA(kStageName[stg]);
         if (!on) return hipSuccess;
         hipEvent_t e;
         hipError_t r = hipEventCreate(&e);
@@ -915,6 +921,7 @@ splotch_status splotch_workspace_size(int64_t n, const splotch_camera *cam,
 splotch_status splotch_render(const splotch_particles *P, const splotch_camera *cam,
                               const splotch_colourmap *cmap, const splotch_params *p,
                               splotch_image *img) {
+    TraceRange trace("splotch_render");
     Ctx c;
     splotch_status st = prepare(P, cam, p, &c);
     if (st != SPLOTCH_OK) return st;
@@ -1043,6 +1050,7 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
                                     const splotch_camera *cams, const splotch_colourmap *cmap,
                                     const splotch_params *p, splotch_image *images,
                                     int32_t use_graph) {
+    TraceRange trace("splotch_render_batch");
     if (n_views < 1 || n_views > SPLOTCH_MAX_VIEWS || !cams || !images || !p)
         return SPLOTCH_E_INVALID_ARG;
     if (use_graph != 0 && use_graph != 1) return SPLOTCH_E_INVALID_ARG;

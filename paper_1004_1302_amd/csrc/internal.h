@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 namespace splotch {
@@ -297,5 +298,14 @@ __device__ __forceinline__ void species_range(const SpeciesDev &sp, const uint32
         }
     }
 }
+
+// A named range on the host timeline of a trace (roctx: rocprofv3
+// --marker-trace shows it; a plain call into a stub when no tool listens).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 }  // namespace splotch

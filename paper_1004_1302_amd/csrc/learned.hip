@@ -374,6 +374,7 @@ splotch_status splotch_render_learned(const splotch_particles *full,
                                       size_t nn_workspace_bytes, const uint8_t *probe_mask,
                                       float psnr_threshold, splotch_image *image,
                                       int32_t *used_fallback, float *probe_psnr) {
+    TraceRange trace("splotch_render_learned");
     if (!full || !dec || !cam || !params || !net || !probe_mask || !image || !image->rgb ||
         !used_fallback || !probe_psnr || params->tile_mask || isnan(psnr_threshold))
         return SPLOTCH_E_INVALID_ARG;

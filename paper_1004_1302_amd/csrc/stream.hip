@@ -267,6 +267,7 @@ splotch_status splotch_stream_workspace_size(const splotch_particles *host, int6
 splotch_status splotch_render_stream(const splotch_particles *host, int64_t subset, int64_t slab,
                                      const splotch_camera *cam, const splotch_colourmap *cmap,
                                      const splotch_params *params, splotch_image *image) {
+    TraceRange trace("splotch_render_stream");
     splotch_status r = validate_host_set(host);
     if (r != SPLOTCH_OK) return r;
     if (!params || !image || !image->rgb || params->tile_mask) return SPLOTCH_E_INVALID_ARG;
