@@ -801,32 +801,52 @@ __global__ __launch_bounds__(64) void k_splat_rows(SplatArgs a) {
 // as they would under the hardware's own dispatch.  Units past the last
 // item end the loop: their run base only grows with the counter.
 template <int T, bool ORDERED, bool KAHAN, bool COUNT, bool K3D, bool GEN>
-__global__ __launch_bounds__(64) void k_splat_rows_multi(const SplatArgs *views, int nv,
-                                                         uint32_t *next) {
+__global__ __launch_bounds__(64) void k_splat_rows_multi(const SplatArgs *__restrict__ views,
+                                                         int nv, uint32_t *next) {
+    // The views' settings are read through the constant address space with
+    // a wave-uniform index, so their fields come in by scalar loads into
+    // scalar registers, as a kernel argument's do.  (Read as global memory,
+    // the fields sit in vector registers, about 24 more, and 5 waves fit on
+    // a SIMD instead of 7.)  Nothing writes them during the launch.
+    typedef const __attribute__((address_space(4))) SplatArgs *ConstArgs;
+    const ConstArgs cviews = (ConstArgs)views;
     uint32_t first[kMaxGroup + 1];
     first[0] = 0;
+#pragma unroll
     for (int v = 0; v < kMaxGroup; ++v) {
         uint32_t n = 0;
         if (v < nv) {
-            const SplatArgs &a = views[v];
-            const uint64_t items = a.seg_off[(uint32_t)(a.ntx * a.nty)];
-            n = (uint32_t)(items < a.max_items ? items : a.max_items);
+            const uint64_t items = cviews[v].seg_off[(uint32_t)(cviews[v].ntx * cviews[v].nty)];
+            n = (uint32_t)(items < cviews[v].max_items ? items : cviews[v].max_items);
         }
         first[v + 1] = first[v] + n;
     }
-    const uint32_t total = first[nv];
+    uint32_t total = first[1];
+#pragma unroll
+    for (int v = 2; v <= kMaxGroup; ++v) total = v <= nv ? first[v] : total;
     const uint32_t x = blockIdx.x & 7u;
     for (;;) {
         uint32_t k = 0;
         if (threadIdx.x == 0) k = atomicAdd(&next[x], 1u);
-        k = (uint32_t)__shfl((int)k, 0, 64);
+        // lane 0's counter value into a scalar register
+        k = __builtin_amdgcn_readfirstlane(k);
         uint32_t item, sub, base;
         unit_of<T>(8u * k + x, &item, &sub, &base);
         if (base >= total) break;
         if (item >= total) continue;
         int v = 0;
-        while (v + 1 < nv && item >= first[v + 1]) ++v;
-        rows_unit<T, ORDERED, KAHAN, COUNT, K3D, GEN>(views[v], item - first[v], sub);
+        uint32_t f = 0;
+#pragma unroll
+        for (int w = 1; w < kMaxGroup; ++w) {
+            if (w < nv && item >= first[w]) {
+                v = w;
+                f = first[w];
+            }
+        }
+        v = __builtin_amdgcn_readfirstlane(v);
+        f = __builtin_amdgcn_readfirstlane(f);
+        rows_unit<T, ORDERED, KAHAN, COUNT, K3D, GEN>(*(const SplatArgs *)(cviews + v), item - f,
+                                                      sub);
         __syncthreads();  // the next unit reuses the staging rows
     }
 }
