@@ -8,6 +8,7 @@
 // (wave ballots find equal digits, lanes in order, waves in order: stable),
 // reorders the tile in LDS and writes each digit run contiguously.
 #include <algorithm>
+#include <atomic>
 
 #include "internal.h"
 
@@ -19,7 +20,7 @@ constexpr int kT = 256;
 constexpr int kW = kT / 64;
 constexpr int kIpt = 16;
 constexpr int kTile = kT * kIpt;  // 4096
-constexpr uint32_t kStrideGrid = 2048;  // workgroups of a pass sized on the device
+constexpr int kMaxDevices = 64;        // striding grids cached per device
 
 __device__ __forceinline__ uint32_t shfl_up_u32(uint32_t v, int o) {
     return (uint32_t)__shfl_up((int)v, o, 64);
@@ -414,27 +415,75 @@ size_t radix_scratch_bytes(size_t n) {
     return hist + scan_u32_scratch_bytes(nb * 256);
 }
 
+// Workgroups of a striding pass: as many as the device holds at once (a
+// multiple of 8, so each keeps its XCD).  A larger grid would leave its
+// last workgroups waiting for the first to finish their whole stride: the
+// scatter's LDS allows 4 workgroups per CU, 1024 on the device.  Cached per
+// device and kernel; 0 when the runtime cannot tell.
+template <typename K>
+uint32_t resident_grid(K kernel, std::atomic<uint32_t> *cache) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    uint32_t g = cache[dev].load(std::memory_order_relaxed);
+    if (g) return g;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kT, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    g = (uint32_t)std::max(per_cu, 1) * (uint32_t)std::max(cus, 1);
+    g = std::max<uint32_t>(g / 8 * 8, 8);
+    cache[dev].store(g, std::memory_order_relaxed);
+    return g;
+}
+
 // One pass: digit histogram per tile, its scan, the scatter.
+struct StrideGrids {
+    uint32_t hist, scatter;
+};
+
+template <int DB>
+StrideGrids stride_grids() {
+    static std::atomic<uint32_t> hist_grid[kMaxDevices], scatter_grid[kMaxDevices];
+    return StrideGrids{resident_grid(k_rs_hist<true, DB>, hist_grid),
+                       resident_grid(k_rs_scatter<true, DB>, scatter_grid)};
+}
+
 template <int DB>
 hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                       size_t n, const uint64_t *n_dev, int shift, uint32_t bias, uint32_t *hist,
-                      uint32_t nb, int write_keys, const uint32_t *tag, uint32_t grid,
-                      void *scan_scratch, hipStream_t s) {
-    if (n_dev)
-        hipLaunchKernelGGL((k_rs_hist<true, DB>), dim3(grid), dim3(kT), 0, s, kin, n, n_dev,
+                      uint32_t nb, int write_keys, const uint32_t *tag, void *scan_scratch,
+                      hipStream_t s) {
+    const StrideGrids sg = n_dev ? stride_grids<DB>() : StrideGrids{0, 0};
+    if (n_dev) {
+        // a count on the device: a grid of resident workgroups striding over
+        // the live tiles
+        const uint32_t g = sg.hist;
+        if (!g) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_rs_hist<true, DB>), dim3(std::min(nb, g)), dim3(kT), 0, s, kin, n,
+                           n_dev, shift, bias, hist, nb);
+    } else {
+        hipLaunchKernelGGL((k_rs_hist<false, DB>), dim3(nb), dim3(kT), 0, s, kin, n, n_dev,
                            shift, bias, hist, nb);
-    else
-        hipLaunchKernelGGL((k_rs_hist<false, DB>), dim3(grid), dim3(kT), 0, s, kin, n, n_dev,
-                           shift, bias, hist, nb);
+    }
     hipError_t e = launch_scan_u32(hist, (size_t)nb << DB, scan_scratch, s);
     if (e != hipSuccess) return e;
-    if (n_dev)
-        hipLaunchKernelGGL((k_rs_scatter<true, DB>), dim3(grid), dim3(kT), 0, s, kin, vin, kout,
+    if (n_dev) {
+        const uint32_t g = sg.scatter;
+        if (!g) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_rs_scatter<true, DB>), dim3(std::min(nb, g)), dim3(kT), 0, s, kin,
+                           vin, kout, vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
+    } else {
+        hipLaunchKernelGGL((k_rs_scatter<false, DB>), dim3(nb), dim3(kT), 0, s, kin, vin, kout,
                            vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
-    else
-        hipLaunchKernelGGL((k_rs_scatter<false, DB>), dim3(grid), dim3(kT), 0, s, kin, vin, kout,
-                           vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
+    }
     return hipGetLastError();
+}
+
+hipError_t radix_prepare_stride_grids() {
+    return stride_grids<7>().hist && stride_grids<7>().scatter && stride_grids<8>().hist &&
+                   stride_grids<8>().scatter
+               ? hipSuccess
+               : hipErrorInvalidValue;
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
@@ -451,9 +500,6 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
     // 7-bit digits when they cover the key in as many passes: half the
     // histogram, and digit runs twice as long in the scatter's writes
     const int db = bits > 0 && bits <= 7 * passes ? 7 : 8;
-    // a count on the device: a capped grid of workgroups striding over the
-    // live tiles (a multiple of 8, so each keeps its XCD)
-    const uint32_t grid = n_dev ? std::min<uint32_t>(nb, kStrideGrid) : nb;
     int src = 0;
     for (int p = 0; p < passes; ++p) {
         uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
@@ -464,9 +510,9 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         const uint32_t *tag = (p == 0 && vals_identity) ? tag_counts : nullptr;
         const int wk = (!last || keys_needed) ? 1 : 0;
         hipError_t e = db == 7 ? radix_pass<7>(kin, vsrc, kout, vout, n, n_dev, shift, bias, hist,
-                                               nb, wk, tag, grid, scan_scratch, s)
+                                               nb, wk, tag, scan_scratch, s)
                                : radix_pass<8>(kin, vsrc, kout, vout, n, n_dev, shift, bias, hist,
-                                               nb, wk, tag, grid, scan_scratch, s);
+                                               nb, wk, tag, scan_scratch, s);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
