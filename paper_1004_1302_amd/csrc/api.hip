@@ -71,8 +71,10 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
         L.val1 = take(N * 4);
     }
     L.off = take((N + 1) * 8);
-    L.split = take(N * 4);  // processing positions of split particles
-    L.split_cnt = take(4);
+    // split particles: a queue part and a count per emission workgroup
+    const size_t emit_groups = (N + kEmitGroup - 1) / kEmitGroup;
+    L.split = take(emit_groups * kEmitGroup * 4);
+    L.split_cnt = take(emit_groups * 4);
     L.scan = take(scan_u32_u64_scratch_bytes(N));
     L.radix = take(radix_scratch_bytes(std::max<size_t>(L.ordered ? N : 0, (size_t)cap)));
     L.counters = take(kCntN * 8);

@@ -4,6 +4,8 @@
 // subsets becomes this per-tile duplication).  Pairs are emitted in
 // processing order (particle index, or front-to-back depth order), so a
 // stable sort by tile leaves every tile's list in that order.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace splotch {
@@ -11,6 +13,7 @@ namespace splotch {
 namespace {
 
 constexpr int kThreads = 256;
+static_assert(kThreads == (int)kEmitGroup, "one split-queue part per emission workgroup");
 
 __global__ void k_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t *dst, size_t n) {
     size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -37,11 +40,8 @@ __device__ __forceinline__ uint32_t pair_key(const EmitArgs &a, int tx, int ty, 
 }
 
 // One thread per particle in processing order writes its pairs at its
-// offset, tile rows bottom to top, tiles left to right.  Particles whose
-// footprint box covers more than split_pixels pixels are split (Section
-// 3.2: a large particle's task divided into several over subsets of its
-// pixels): they are queued and their pairs written by a whole workgroup
-// in k_emit_split, into the same slots.
+// offset, tile rows bottom to top, tiles left to right, skipping the tiles
+// a tile mask leaves out.  Used with a tile mask; no particle is split.
 __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     const uint64_t k = a.first + (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (k >= a.last) return;
@@ -50,15 +50,6 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
     if (c == 0) return;
     const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
     const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
-    if (a.split_list) {
-        const uint64_t bw = ((bb.x >> kBboxBits) & kBboxMask) - (bb.x & kBboxMask) + 1;
-        const uint64_t bh = ((bb.y >> kBboxBits) & kBboxMask) - (bb.y & kBboxMask) + 1;
-        if (bw * bh > a.split_pixels) {
-            const uint32_t q = atomicAdd(a.split_count, 1u);
-            a.split_list[q] = (uint32_t)k;
-            return;
-        }
-    }
     const int T = a.tile;
     const int tx0 = (int)(bb.x & kBboxMask) / T, tx1 = (int)((bb.x >> kBboxBits) & kBboxMask) / T;
     const int ty0 = (int)(bb.y & kBboxMask) / T, ty1 = (int)((bb.y >> kBboxBits) & kBboxMask) / T;
@@ -79,28 +70,152 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
         }
 }
 
-// Split particles: workgroups take queued particles in turn and write
-// pair t of a particle (its t-th tile, in k_emit's order) at offset + t.
-// Only used without a tile mask, where pair t is tile t of the box.
-__global__ __launch_bounds__(kThreads) void k_emit_split(EmitArgs a) {
-    const uint32_t nq = *a.split_count;
-    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
-        const uint64_t k = a.split_list[q];
-        const uint64_t o0 = a.off[k];
-        const uint32_t c = (uint32_t)(a.off[k + 1] - o0);
-        const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
-        const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
-        const int T = a.tile;
-        const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
-        const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
-        const int tx0 = i0 / T, ty0 = j0 / T, nx = i1 / T - tx0 + 1;
-        const uint64_t o = o0 - a.base;
-        if (o + c > a.cap && a.overflow && threadIdx.x == 0) *a.overflow = 1u;
-        for (uint32_t t = threadIdx.x; t < c; t += kThreads) {
-            if (o + t >= a.cap) break;
-            const int tx = tx0 + (int)(t % (uint32_t)nx), ty = ty0 + (int)(t / (uint32_t)nx);
-            a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1);
-            a.pair_val[o + t] = i;
+// The same pairs written by waves: a wave takes 64 consecutive processing
+// positions, whose pairs fill one run of slots, and lane l writes the
+// run's slots l, l + 64, ...  A slot's particle is the last of the wave's
+// 64 whose first slot is at or before it (a binary search over the first
+// slots, kept in LDS), and its tile is the slot's rank in that particle's
+// box in k_emit's order (rows bottom to top, tiles left to right).  Every
+// lane then does the same work however unevenly the tile counts spread,
+// and each store writes consecutive slots.  Split particles are left out
+// of the run (their slots are written by k_emit_split) and queued in the
+// workgroup's own part of the split list, counted in LDS: a counter shared
+// by the whole grid would take one device-scope atomic per queue step, and
+// those are serialised beyond the XCDs' L2 caches.  Used without a tile
+// mask, where a particle's t-th pair is the t-th tile of its box.
+__global__ __launch_bounds__(kThreads) void k_emit_waves(EmitArgs a) {
+    __shared__ uint32_t s_first[kThreads];  // first slot in the wave's run
+    __shared__ uint32_t s_off[kThreads];    // first slot, from the wave's first pair
+    __shared__ uint32_t s_b0[kThreads], s_b1[kThreads], s_idx[kThreads];
+    __shared__ uint32_t s_nsplit;
+    if (threadIdx.x == 0) s_nsplit = 0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t w0 = threadIdx.x & ~63u;
+    const uint64_t k0 = a.first + (uint64_t)blockIdx.x * kThreads + w0;
+    const uint64_t k = k0 + lane;
+    const bool valid = k < a.last;
+    uint64_t o0 = 0;
+    uint32_t c = 0, i = 0;
+    bool split = false;
+    uint2 bb = make_uint2(0u, 0u);
+    if (valid) {
+        o0 = a.off[k];
+        c = (uint32_t)(a.off[k + 1] - o0);
+        if (c) {
+            i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
+            bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
+            if (a.split_list) {
+                const uint64_t bw = ((bb.x >> kBboxBits) & kBboxMask) - (bb.x & kBboxMask) + 1;
+                const uint64_t bh = ((bb.y >> kBboxBits) & kBboxMask) - (bb.y & kBboxMask) + 1;
+                split = bw * bh > a.split_pixels;
+            }
+            if (split) {
+                const uint32_t q = atomicAdd(&s_nsplit, 1u);
+                a.split_list[(size_t)blockIdx.x * kThreads + q] = (uint32_t)k;
+            } else if (o0 - a.base + c > a.cap && a.overflow) {
+                *a.overflow = 1u;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && a.split_list) a.split_count[blockIdx.x] = s_nsplit;
+    if (k0 >= a.last) return;  // the whole wave is past the end
+    // the wave's run: its particles' slots in order, split ones left out
+    // (at most 64 particles of at most (16384 / 8)^2 tiles each)
+    const uint32_t ce = split ? 0u : c;
+    uint32_t incl = ce;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
+        if ((int)lane >= d) incl += t;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+    const uint64_t wb = a.off[k0];
+    s_first[threadIdx.x] = incl - ce;
+    s_off[threadIdx.x] = (uint32_t)(o0 - wb);
+    s_b0[threadIdx.x] = bb.x;
+    s_b1[threadIdx.x] = bb.y;
+    s_idx[threadIdx.x] = i;
+    // the wave reads back its own entries (a wave's LDS requests complete
+    // in order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int T = a.tile;
+    const uint64_t slot0 = wb - a.base;
+    for (uint32_t j = lane; j < total; j += 64) {
+        // lane 0's first slot is 0 and the first slots never decrease; a
+        // particle without slots in the run shares its first slot with the
+        // next particle, which the search then takes
+        uint32_t p = 0;
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1)
+            if (s_first[w0 + p + step] <= j) p += step;
+        const uint32_t e = w0 + p;
+        const uint32_t t = j - s_first[e];
+        const uint64_t slot = slot0 + s_off[e] + t;
+        if (slot >= a.cap) continue;
+        const uint32_t b0 = s_b0[e], b1 = s_b1[e];
+        const int i0 = (int)(b0 & kBboxMask), i1 = (int)((b0 >> kBboxBits) & kBboxMask);
+        const int j0 = (int)(b1 & kBboxMask), j1 = (int)((b1 >> kBboxBits) & kBboxMask);
+        const int tx0 = i0 / T, ty0 = j0 / T;
+        const uint32_t nx = (uint32_t)(i1 / T - tx0 + 1);
+        const uint32_t row = t / nx;
+        const int tx = tx0 + (int)(t - row * nx), ty = ty0 + (int)row;
+        a.pair_key[slot] = pair_key(a, tx, ty, i0, i1, j0, j1);
+        a.pair_val[slot] = s_idx[e];
+    }
+}
+
+// Split particles: each k_emit_waves workgroup b queued split_count[b] of
+// them at split_list[b * 256 ...].  A workgroup here reads the counts of 64
+// such workgroups at a time; its waves take the queued particles in turn,
+// and a wave's lanes write pair t of its particle (its t-th tile, in
+// k_emit's order) at the particle's offset + t.
+constexpr uint32_t kSplitChunk = 64;
+
+__global__ __launch_bounds__(kThreads) void k_emit_split(EmitArgs a, uint32_t nblocks) {
+    __shared__ uint32_t s_pre[kSplitChunk + 1];  // queued particles before each part
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    constexpr uint32_t kWaves = kThreads / 64;
+    for (uint32_t c0 = blockIdx.x * kSplitChunk; c0 < nblocks; c0 += gridDim.x * kSplitChunk) {
+        __syncthreads();  // the previous chunk's prefix is read
+        if (wave == 0) {
+            const uint32_t m = c0 + lane < nblocks ? a.split_count[c0 + lane] : 0u;
+            uint32_t incl = m;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
+                if ((int)lane >= d) incl += t;
+            }
+            s_pre[lane + 1] = incl;
+            if (lane == 0) s_pre[0] = 0;
+        }
+        __syncthreads();
+        const uint32_t total = s_pre[kSplitChunk];
+        for (uint32_t e = wave; e < total; e += kWaves) {
+            // the part holding entry e: the last u with s_pre[u] <= e
+            uint32_t u = 0;
+#pragma unroll
+            for (uint32_t step = 32; step > 0; step >>= 1)
+                if (s_pre[u + step] <= e) u += step;
+            const uint64_t k = a.split_list[(size_t)(c0 + u) * kThreads + (e - s_pre[u])];
+            const uint64_t o0 = a.off[k];
+            const uint32_t c = (uint32_t)(a.off[k + 1] - o0);
+            const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
+            const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
+            const int T = a.tile;
+            const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
+            const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
+            const int tx0 = i0 / T, ty0 = j0 / T, nx = i1 / T - tx0 + 1;
+            const uint64_t o = o0 - a.base;
+            if (o + c > a.cap && a.overflow && lane == 0) *a.overflow = 1u;
+            for (uint32_t t = lane; t < c; t += 64) {
+                if (o + t >= a.cap) break;
+                const int tx = tx0 + (int)(t % (uint32_t)nx), ty = ty0 + (int)(t / (uint32_t)nx);
+                a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1);
+                a.pair_val[o + t] = i;
+            }
         }
     }
 }
@@ -199,15 +314,16 @@ hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
     if (n == 0) return hipSuccess;
     EmitArgs e = a;
     if (e.tile_mask) e.split_list = nullptr;  // split only where pair t is tile t
-    if (e.split_list) {
-        hipError_t r = launch_fill_u32(e.split_count, 0u, 1, s);
-        if (r != hipSuccess) return r;
-    }
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       s, e);
+    const uint32_t nblocks = (uint32_t)((n + kThreads - 1) / kThreads);
+    if (e.tile_mask)
+        hipLaunchKernelGGL(k_emit, dim3(nblocks), dim3(kThreads), 0, s, e);
+    else
+        hipLaunchKernelGGL(k_emit_waves, dim3(nblocks), dim3(kThreads), 0, s, e);
     hipError_t r = hipGetLastError();
     if (r != hipSuccess || !e.split_list) return r;
-    hipLaunchKernelGGL(k_emit_split, dim3(2048), dim3(kThreads), 0, s, e);
+    const uint32_t chunks = (nblocks + kSplitChunk - 1) / kSplitChunk;
+    hipLaunchKernelGGL(k_emit_split, dim3(std::min<uint32_t>(chunks, 2048)), dim3(kThreads), 0,
+                       s, e, nblocks);
     return hipGetLastError();
 }
 

@@ -152,12 +152,15 @@ struct EmitArgs {
     int qshift;                // > 0: key bit qshift + b set when the box meets 8x8 block b
     uint32_t *pair_key, *pair_val;
     // split particles: boxes of more than split_pixels pixels are queued
-    // (split_list, capacity last - first; null = no splitting) and emitted
-    // by whole workgroups
+    // and emitted by whole workgroups.  Emission workgroup b (256
+    // positions) queues its split particles at split_list[256 b ...] and
+    // their number at split_count[b]: capacities of 256 and 1 entries per
+    // workgroup of the launch (null split_list = no splitting).
     uint64_t split_pixels;
     uint32_t *split_list;    // processing positions (n < 2^32)
     uint32_t *split_count;
 };
+constexpr uint32_t kEmitGroup = 256;  // positions per emission workgroup
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
 // Bit of a pair key where the mask of the tile's 8x8 blocks that the
 // particle's box meets begins (bit qshift + b for block b, row-major), or 0
