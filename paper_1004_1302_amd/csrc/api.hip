@@ -27,7 +27,7 @@ static_assert(kMaxLanes <= kMaxGroup, "a persistent group holds one view per lan
 struct Layout {
     size_t rec, cnt, key0, key1, val0, val1, off, scan, radix, counters, range, bounds;
     size_t tstart, tend, mcount, seg_len, nseg, nmulti, seg_off, part_off, seg_scan, item_tile;
-    size_t partial, flags, sargs, unit_next, split, split_cnt;
+    size_t partial, flags, sargs, unit_next, split, split_cnt, split_off;
     size_t pk0, pk1, pv0, pv1;
     uint64_t max_items, max_slots;
     size_t total;
@@ -71,10 +71,13 @@ Layout layout(int64_t n, const splotch_camera *cam, const splotch_params *p, uin
         L.val1 = take(N * 4);
     }
     L.off = take((N + 1) * 8);
-    // split particles: a queue part and a count per emission workgroup
+    // split particles: a queue part and a count per emission workgroup and
+    // the counts' scan (the dense queue reuses cnt, which the pair-offset
+    // scan has consumed by then, and the scan's scratch that of that scan)
     const size_t emit_groups = (N + kEmitGroup - 1) / kEmitGroup;
     L.split = take(emit_groups * kEmitGroup * 4);
     L.split_cnt = take(emit_groups * 4);
+    L.split_off = take((emit_groups + 1) * 8);
     L.scan = take(scan_u32_u64_scratch_bytes(N));
     L.radix = take(radix_scratch_bytes(std::max<size_t>(L.ordered ? N : 0, (size_t)cap)));
     L.counters = take(kCntN * 8);
@@ -484,6 +487,9 @@ splotch_status run_bin_chunk(const Ctx &c, const uint32_t *order, uint32_t idx_m
     e.split_pixels = c.split;
     e.split_list = c.split ? c.at<uint32_t>(c.L.split) : nullptr;
     e.split_count = c.at<uint32_t>(c.L.split_cnt);
+    e.split_off = c.at<uint64_t>(c.L.split_off);
+    e.split_scratch = c.at<void>(c.L.scan);
+    e.split_dense = c.at<uint32_t>(c.L.cnt);
     TRY(launch_emit(e, c.s));
     TRY(const_cast<Prof &>(c.prof).mark(3));
     int bits = 0;
@@ -710,6 +716,9 @@ splotch_status enqueue_view(Ctx &c, int32_t v, uint32_t *flags, uint64_t *totals
         e.split_pixels = split_threshold(p, cam);
         e.split_list = e.split_pixels ? c.at<uint32_t>(c.L.split) : nullptr;
         e.split_count = c.at<uint32_t>(c.L.split_cnt);
+        e.split_off = c.at<uint64_t>(c.L.split_off);
+        e.split_scratch = c.at<void>(c.L.scan);
+        e.split_dense = c.at<uint32_t>(c.L.cnt);
         uint32_t *pk0 = c.at<uint32_t>(c.L.pk0), *pk1 = c.at<uint32_t>(c.L.pk1);
         uint32_t *pv0 = c.at<uint32_t>(c.L.pv0), *pv1 = c.at<uint32_t>(c.L.pv1);
         e.pair_key = pk0;

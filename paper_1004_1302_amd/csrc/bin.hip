@@ -80,8 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
 // and each store writes consecutive slots.  Split particles are left out
 // of the run (their slots are written by k_emit_split) and queued in the
 // workgroup's own part of the split list, counted in LDS: a counter shared
-// by the whole grid would take one device-scope atomic per queue step, and
-// those are serialised beyond the XCDs' L2 caches.  Used without a tile
+// by the whole grid would take one device-scope atomic per queued particle
+// or wave, and those are serialised beyond the XCDs' L2 caches.  Used without a tile
 // mask, where a particle's t-th pair is the t-th tile of its box.
 __global__ __launch_bounds__(kThreads) void k_emit_waves(EmitArgs a) {
     __shared__ uint32_t s_first[kThreads];  // first slot in the wave's run
@@ -167,55 +167,41 @@ __global__ __launch_bounds__(kThreads) void k_emit_waves(EmitArgs a) {
     }
 }
 
-// Split particles: each k_emit_waves workgroup b queued split_count[b] of
-// them at split_list[b * 256 ...].  A workgroup here reads the counts of 64
-// such workgroups at a time; its waves take the queued particles in turn,
-// and a wave's lanes write pair t of its particle (its t-th tile, in
-// k_emit's order) at the particle's offset + t.
-constexpr uint32_t kSplitChunk = 64;
+// The queued split particles into one dense queue: thread b copies the
+// part of emission workgroup b to its place in the counts' scan.
+__global__ void k_split_compact(EmitArgs a, uint32_t nblocks) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    const uint32_t m = a.split_count[b];
+    const uint64_t o = a.split_off[b];
+    for (uint32_t q = 0; q < m; ++q) a.split_dense[o + q] = a.split_list[(size_t)b * kThreads + q];
+}
 
+// Split particles: the waves of the grid take the dense queue's particles
+// in turn, and a wave's lanes write pair t of its particle (its t-th tile,
+// in k_emit's order) at the particle's offset + t.
 __global__ __launch_bounds__(kThreads) void k_emit_split(EmitArgs a, uint32_t nblocks) {
-    __shared__ uint32_t s_pre[kSplitChunk + 1];  // queued particles before each part
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    constexpr uint32_t kWaves = kThreads / 64;
-    for (uint32_t c0 = blockIdx.x * kSplitChunk; c0 < nblocks; c0 += gridDim.x * kSplitChunk) {
-        __syncthreads();  // the previous chunk's prefix is read
-        if (wave == 0) {
-            const uint32_t m = c0 + lane < nblocks ? a.split_count[c0 + lane] : 0u;
-            uint32_t incl = m;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
-                if ((int)lane >= d) incl += t;
-            }
-            s_pre[lane + 1] = incl;
-            if (lane == 0) s_pre[0] = 0;
-        }
-        __syncthreads();
-        const uint32_t total = s_pre[kSplitChunk];
-        for (uint32_t e = wave; e < total; e += kWaves) {
-            // the part holding entry e: the last u with s_pre[u] <= e
-            uint32_t u = 0;
-#pragma unroll
-            for (uint32_t step = 32; step > 0; step >>= 1)
-                if (s_pre[u + step] <= e) u += step;
-            const uint64_t k = a.split_list[(size_t)(c0 + u) * kThreads + (e - s_pre[u])];
-            const uint64_t o0 = a.off[k];
-            const uint32_t c = (uint32_t)(a.off[k + 1] - o0);
-            const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
-            const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
-            const int T = a.tile;
-            const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
-            const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
-            const int tx0 = i0 / T, ty0 = j0 / T, nx = i1 / T - tx0 + 1;
-            const uint64_t o = o0 - a.base;
-            if (o + c > a.cap && a.overflow && lane == 0) *a.overflow = 1u;
-            for (uint32_t t = lane; t < c; t += 64) {
-                if (o + t >= a.cap) break;
-                const int tx = tx0 + (int)(t % (uint32_t)nx), ty = ty0 + (int)(t / (uint32_t)nx);
-                a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1);
-                a.pair_val[o + t] = i;
-            }
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t total = a.split_off[nblocks];
+    const uint64_t waves = (uint64_t)gridDim.x * (kThreads / 64);
+    for (uint64_t e = (uint64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); e < total;
+         e += waves) {
+        const uint64_t k = a.split_dense[e];
+        const uint64_t o0 = a.off[k];
+        const uint32_t c = (uint32_t)(a.off[k + 1] - o0);
+        const uint32_t i = a.order ? (a.order[k] & a.idx_mask) : (uint32_t)k;
+        const uint2 bb = *reinterpret_cast<const uint2 *>(&a.rec[i].a);
+        const int T = a.tile;
+        const int i0 = (int)(bb.x & kBboxMask), i1 = (int)((bb.x >> kBboxBits) & kBboxMask);
+        const int j0 = (int)(bb.y & kBboxMask), j1 = (int)((bb.y >> kBboxBits) & kBboxMask);
+        const int tx0 = i0 / T, ty0 = j0 / T, nx = i1 / T - tx0 + 1;
+        const uint64_t o = o0 - a.base;
+        if (o + c > a.cap && a.overflow && lane == 0) *a.overflow = 1u;
+        for (uint32_t t = lane; t < c; t += 64) {
+            if (o + t >= a.cap) break;
+            const int tx = tx0 + (int)(t % (uint32_t)nx), ty = ty0 + (int)(t / (uint32_t)nx);
+            a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1);
+            a.pair_val[o + t] = i;
         }
     }
 }
@@ -321,9 +307,13 @@ hipError_t launch_emit(const EmitArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_emit_waves, dim3(nblocks), dim3(kThreads), 0, s, e);
     hipError_t r = hipGetLastError();
     if (r != hipSuccess || !e.split_list) return r;
-    const uint32_t chunks = (nblocks + kSplitChunk - 1) / kSplitChunk;
-    hipLaunchKernelGGL(k_emit_split, dim3(std::min<uint32_t>(chunks, 2048)), dim3(kThreads), 0,
-                       s, e, nblocks);
+    if ((r = launch_scan_u32_u64(e.split_count, e.split_off, nblocks, e.split_scratch, s)) !=
+        hipSuccess)
+        return r;
+    hipLaunchKernelGGL(k_split_compact, dim3((nblocks + kThreads - 1) / kThreads), dim3(kThreads),
+                       0, s, e, nblocks);
+    if ((r = hipGetLastError()) != hipSuccess) return r;
+    hipLaunchKernelGGL(k_emit_split, dim3(2048), dim3(kThreads), 0, s, e, nblocks);
     return hipGetLastError();
 }
 

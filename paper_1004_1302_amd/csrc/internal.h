@@ -152,13 +152,19 @@ struct EmitArgs {
     int qshift;                // > 0: key bit qshift + b set when the box meets 8x8 block b
     uint32_t *pair_key, *pair_val;
     // split particles: boxes of more than split_pixels pixels are queued
-    // and emitted by whole workgroups.  Emission workgroup b (256
-    // positions) queues its split particles at split_list[256 b ...] and
-    // their number at split_count[b]: capacities of 256 and 1 entries per
-    // workgroup of the launch (null split_list = no splitting).
+    // and their pairs written a wave per particle.  Emission workgroup b
+    // (256 positions) queues its split particles at split_list[256 b ...]
+    // and their number at split_count[b] (capacities of 256 and 1 entries
+    // per workgroup of the launch; null split_list = no splitting); the
+    // counts' exclusive scan (split_off, one entry more, with
+    // split_scratch for launch_scan_u32_u64) places them in one dense
+    // queue (split_dense, last - first entries).
     uint64_t split_pixels;
     uint32_t *split_list;    // processing positions (n < 2^32)
     uint32_t *split_count;
+    uint64_t *split_off;
+    void *split_scratch;
+    uint32_t *split_dense;
 };
 constexpr uint32_t kEmitGroup = 256;  // positions per emission workgroup
 hipError_t launch_emit(const EmitArgs &a, hipStream_t s);
