@@ -160,6 +160,58 @@ __global__ __launch_bounds__(kT) void k_scan_down(L in, TO *out, size_t n, const
     }
 }
 
+// A scan of at most kSmallTiles tiles in one workgroup: the tiles one after
+// another, each as in k_scan_down with the running total as its partial.
+// One launch instead of three for the short scans (digit histograms and
+// segment counts of small views, where launches dominate).
+constexpr size_t kSmallTiles = 4;
+
+template <typename L, typename TO>
+__global__ __launch_bounds__(kT) void k_scan_small(L in, TO *out, size_t n, TO *total_out) {
+    __shared__ TO s[kTile + kTile / 16];
+    __shared__ TO s_w[kW];
+    TO carry = 0;
+    for (size_t base = 0; base < n; base += kTile) {
+        decltype(in.raw(0)) r[kIpt];
+#pragma unroll
+        for (int q = 0; q < kIpt; ++q) {
+            size_t idx = base + (size_t)q * kT + threadIdx.x;
+            if (idx < n) r[q] = in.raw(idx);
+        }
+#pragma unroll
+        for (int q = 0; q < kIpt; ++q) {
+            int l = q * kT + threadIdx.x;
+            size_t idx = base + l;
+            s[pad(l)] = idx < n ? (TO)in.finish(r[q]) : (TO)0;
+        }
+        __syncthreads();
+        TO v[kIpt];
+        TO sum = 0;
+#pragma unroll
+        for (int i = 0; i < kIpt; ++i) {
+            v[i] = s[pad(threadIdx.x * kIpt + i)];
+            sum += v[i];
+        }
+        TO tot;
+        TO run = carry + block_excl_scan<kW>(sum, s_w, &tot);
+#pragma unroll
+        for (int i = 0; i < kIpt; ++i) {
+            s[pad(threadIdx.x * kIpt + i)] = run;
+            run += v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kIpt; ++q) {
+            int l = q * kT + threadIdx.x;
+            size_t idx = base + l;
+            if (idx < n) out[idx] = s[pad(l)];
+        }
+        carry += tot;
+        __syncthreads();  // before the next tile overwrites s
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
 template <typename TO>
 __global__ void k_set_value(TO *p, TO v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -172,6 +224,10 @@ hipError_t scan_impl(L in, TO *out, size_t n, TO *total_out, void *scratch, hipS
         return hipGetLastError();
     }
     size_t nb = (n + kTile - 1) / kTile;
+    if (nb <= kSmallTiles) {
+        hipLaunchKernelGGL((k_scan_small<L, TO>), dim3(1), dim3(kT), 0, s, in, out, n, total_out);
+        return hipGetLastError();
+    }
     TO *partial = reinterpret_cast<TO *>(scratch);
     hipLaunchKernelGGL((k_scan_reduce<L, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, n,
                        partial);
