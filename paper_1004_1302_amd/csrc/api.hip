@@ -440,8 +440,11 @@ splotch_status run_order_and_scan(const Ctx &c, int64_t n, bool trim_keys,
             }
         }
         const bool tag = (uint64_t)n <= (1ull << kTagShift);
+        // without the read-back, the passes find the key range on the device
+        const uint32_t *key_range =
+            trim_keys ? nullptr : c.at<uint32_t>(c.L.range) + 2 * kMaxSpecies;
         TRY(radix_sort_pairs(k0, v0, k1, v1, true, (size_t)n, nullptr, bits, bias, false,
-                             c.at<void>(c.L.radix), &in1, c.s, tag ? cnt : nullptr));
+                             c.at<void>(c.L.radix), &in1, c.s, tag ? cnt : nullptr, key_range));
         const uint32_t *ord = in1 ? v1 : v0;
         *order = ord;
         if (tag) {

@@ -121,10 +121,14 @@ size_t radix_scratch_bytes(size_t n);
 // tag_counts (with vals_identity, n <= 2^30): the identity values carry the
 // element's count from tag_counts in bits 30-31 (1, 2, 4; 0 = other), so a
 // sorted order also gives the counts in that order without a gather.
+// key_range (device [smallest, largest] key, with n on the host, values
+// only): instead of bits and bias, the passes take the bias and the number
+// of 8-bit digits from the range on the device, and the values land in v0.
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
                             uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
-                            hipStream_t s, const uint32_t *tag_counts = nullptr);
+                            hipStream_t s, const uint32_t *tag_counts = nullptr,
+                            const uint32_t *key_range = nullptr);
 // Look up (once per device) the grids of the passes that take their count
 // on the device, so that no occupancy query runs under graph capture.
 hipError_t radix_prepare_stride_grids();

@@ -271,6 +271,30 @@ struct PassTiles {
     }
 };
 
+// A sort whose key range is on the device (the views of a batch, where
+// nothing is read back): the passes subtract the smallest key and sort as
+// many digits as the range spans; the remaining pass slots return at once.
+// The values go from slot to slot so that the last sorting pass writes v0,
+// and that pass writes no keys.
+struct DeviceKeys {
+    const uint32_t *range;  // [smallest, largest] key (smallest > largest: none); null: host plan
+    uint32_t *v0, *v1;
+    int slot;
+    // false when this slot has nothing to sort
+    __device__ bool resolve(int db, uint32_t *bias, int *passes) const {
+        const uint32_t lo = range[0], hi = range[1];
+        int bits = 1;
+        *bias = 0;
+        if (lo <= hi) {
+            *bias = lo;
+            const uint32_t span = hi - lo;
+            bits = span == 0 ? 1 : 32 - __clz((int)span);
+        }
+        *passes = (bits + db - 1) / db;
+        return slot < *passes;
+    }
+};
+
 // Digit histogram of one tile.  16 copies of the counters (by lane mod 16)
 // keep a wave whose keys share a digit from serialising on one LDS address.
 constexpr int kHistCopies = 16;
@@ -281,8 +305,12 @@ constexpr int kHistCopies = 16;
 template <bool STRIDE, int DB>
 __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_cap,
                                                 const uint64_t *n_dev, int shift, uint32_t bias,
-                                                uint32_t *hist, uint32_t nblocks) {
+                                                uint32_t *hist, uint32_t nblocks, DeviceKeys dk) {
     constexpr uint32_t ND = 1u << DB, DM = ND - 1u;
+    if (dk.range) {
+        int passes;
+        if (!dk.resolve(DB, &bias, &passes)) return;
+    }
     const size_t n = live_count(n_cap, n_dev);
     const PassTiles pt(n, nblocks);
     __shared__ uint32_t sh[kHistCopies][ND];
@@ -417,9 +445,16 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
                                                    const uint64_t *n_dev, int shift,
                                                    uint32_t bias, const uint32_t *hist,
                                                    uint32_t nblocks, int write_keys,
-                                                   const uint32_t *tag) {
+                                                   const uint32_t *tag, DeviceKeys dk) {
     const size_t n = live_count(n_cap, n_dev);
     __shared__ ScatterLds<DB> L;
+    if (dk.range) {
+        int passes;
+        if (!dk.resolve(DB, &bias, &passes)) return;
+        if (dk.slot > 0) vin = ((passes - dk.slot) & 1) ? dk.v1 : dk.v0;
+        vout = ((passes - 1 - dk.slot) & 1) ? dk.v1 : dk.v0;
+        if (dk.slot == passes - 1) write_keys = 0;
+    }
     // the runs two neighbouring tiles write for one digit are adjacent in
     // the output
     if (!STRIDE) {
@@ -507,8 +542,8 @@ StrideGrids stride_grids() {
 template <int DB>
 hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                       size_t n, const uint64_t *n_dev, int shift, uint32_t bias, uint32_t *hist,
-                      uint32_t nb, int write_keys, const uint32_t *tag, void *scan_scratch,
-                      hipStream_t s) {
+                      uint32_t nb, int write_keys, const uint32_t *tag, DeviceKeys dk,
+                      void *scan_scratch, hipStream_t s) {
     const StrideGrids sg = n_dev ? stride_grids<DB>() : StrideGrids{0, 0};
     if (n_dev) {
         // a count on the device: a grid of resident workgroups striding over
@@ -516,10 +551,10 @@ hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, 
         const uint32_t g = sg.hist;
         if (!g) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_rs_hist<true, DB>), dim3(std::min(nb, g)), dim3(kT), 0, s, kin, n,
-                           n_dev, shift, bias, hist, nb);
+                           n_dev, shift, bias, hist, nb, dk);
     } else {
         hipLaunchKernelGGL((k_rs_hist<false, DB>), dim3(nb), dim3(kT), 0, s, kin, n, n_dev,
-                           shift, bias, hist, nb);
+                           shift, bias, hist, nb, dk);
     }
     hipError_t e = launch_scan_u32(hist, (size_t)nb << DB, scan_scratch, s);
     if (e != hipSuccess) return e;
@@ -527,10 +562,10 @@ hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, 
         const uint32_t g = sg.scatter;
         if (!g) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_rs_scatter<true, DB>), dim3(std::min(nb, g)), dim3(kT), 0, s, kin,
-                           vin, kout, vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
+                           vin, kout, vout, n, n_dev, shift, bias, hist, nb, write_keys, tag, dk);
     } else {
         hipLaunchKernelGGL((k_rs_scatter<false, DB>), dim3(nb), dim3(kT), 0, s, kin, vin, kout,
-                           vout, n, n_dev, shift, bias, hist, nb, write_keys, tag);
+                           vout, n, n_dev, shift, bias, hist, nb, write_keys, tag, dk);
     }
     return hipGetLastError();
 }
@@ -545,17 +580,20 @@ hipError_t radix_prepare_stride_grids() {
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
                             bool vals_identity, size_t n, const uint64_t *n_dev, int bits,
                             uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
-                            hipStream_t s, const uint32_t *tag_counts) {
+                            hipStream_t s, const uint32_t *tag_counts,
+                            const uint32_t *key_range) {
     *result_in_1 = false;
     if (n == 0) return hipSuccess;
+    if (key_range && (keys_needed || n_dev)) return hipErrorInvalidValue;
     const uint32_t nb = (uint32_t)((n + kTile - 1) / kTile);
     uint32_t *hist = reinterpret_cast<uint32_t *>(scratch);
     void *scan_scratch =
         reinterpret_cast<char *>(scratch) + align_up((size_t)nb * 256 * sizeof(uint32_t), 256);
+    if (key_range) bits = 32;  // the passes the range needs are found on the device
     const int passes = bits <= 0 ? 1 : (bits + 7) / 8;
     // 7-bit digits when they cover the key in as many passes: half the
     // histogram, and digit runs twice as long in the scatter's writes
-    const int db = bits > 0 && bits <= 7 * passes ? 7 : 8;
+    const int db = !key_range && bits > 0 && bits <= 7 * passes ? 7 : 8;
     int src = 0;
     for (int p = 0; p < passes; ++p) {
         uint32_t *kin = src ? k1 : k0, *vin = src ? v1 : v0;
@@ -565,14 +603,16 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
         const uint32_t *vsrc = (p == 0 && vals_identity) ? (const uint32_t *)nullptr : vin;
         const uint32_t *tag = (p == 0 && vals_identity) ? tag_counts : nullptr;
         const int wk = (!last || keys_needed) ? 1 : 0;
+        const DeviceKeys dk{key_range, v0, v1, p};
         hipError_t e = db == 7 ? radix_pass<7>(kin, vsrc, kout, vout, n, n_dev, shift, bias, hist,
-                                               nb, wk, tag, scan_scratch, s)
+                                               nb, wk, tag, dk, scan_scratch, s)
                                : radix_pass<8>(kin, vsrc, kout, vout, n, n_dev, shift, bias, hist,
-                                               nb, wk, tag, scan_scratch, s);
+                                               nb, wk, tag, dk, scan_scratch, s);
         if (e != hipSuccess) return e;
         src ^= 1;
     }
-    *result_in_1 = src == 1;
+    // a device plan leaves the values in v0
+    *result_in_1 = !key_range && src == 1;
     return hipSuccess;
 }
 
