@@ -21,19 +21,32 @@ __global__ void k_gather_u32(const uint32_t *src, const uint32_t *idx, uint32_t 
         dst[k] = src[idx[k]];
 }
 
-// The pair key of tile (tx, ty) for a particle box [i0, i1] x [j0, j1]:
-// the tile index, and above it (qshift > 0) the mask of the tile's 8x8
-// blocks the box meets (a rectangle of them).
+// The pair key of tile (tx, ty) for a particle box [i0, i1] x [j0, j1]
+// (its second record word b1 carries the corner bits): the tile index, and
+// above it (qshift > 0) the mask of the tile's 8x8 blocks the box meets (a
+// rectangle of them), less the box's corner blocks in this tile that the
+// corner bits mark as holding no pixel within the radius.
 __device__ __forceinline__ uint32_t pair_key(const EmitArgs &a, int tx, int ty, int i0, int i1,
-                                             int j0, int j1) {
+                                             int j0, int j1, uint32_t b1) {
     const int T = a.tile, QW = T / 8;
     uint32_t key = (uint32_t)(ty * a.ntx + tx);
     if (a.qshift) {
-        const int qx0 = (max(i0, tx * T) - tx * T) >> 3, qx1 = (min(i1, tx * T + T - 1) - tx * T) >> 3;
-        const int qy0 = (max(j0, ty * T) - ty * T) >> 3, qy1 = (min(j1, ty * T + T - 1) - ty * T) >> 3;
+        const int x0 = tx * T, y0 = ty * T;
+        const int qx0 = (max(i0, x0) - x0) >> 3, qx1 = (min(i1, x0 + T - 1) - x0) >> 3;
+        const int qy0 = (max(j0, y0) - y0) >> 3, qy1 = (min(j1, y0 + T - 1) - y0) >> 3;
         const uint32_t row = ((2u << qx1) - 1u) & ~((1u << qx0) - 1u);
         uint32_t m = 0;
         for (int qy = qy0; qy <= qy1; ++qy) m |= row << (qy * QW);
+        const uint32_t cb = b1 >> kCornerShift;
+        if (cb) {
+            // a box corner lies in this tile when the box's edges do
+            const bool lo_x = i0 >= x0, hi_x = i1 <= x0 + T - 1;
+            const bool lo_y = j0 >= y0, hi_y = j1 <= y0 + T - 1;
+            if ((cb & 1u) && lo_x && lo_y) m &= ~(1u << (qy0 * QW + qx0));
+            if ((cb & 2u) && hi_x && lo_y) m &= ~(1u << (qy0 * QW + qx1));
+            if ((cb & 4u) && lo_x && hi_y) m &= ~(1u << (qy1 * QW + qx0));
+            if ((cb & 8u) && hi_x && hi_y) m &= ~(1u << (qy1 * QW + qx1));
+        }
         key |= m << a.qshift;
     }
     return key;
@@ -64,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_emit(EmitArgs a) {
         for (int tx = tx0; tx <= tx1; ++tx) {
             if (a.tile_mask && !a.tile_mask[ty * a.ntx + tx]) continue;
             if (o >= a.cap) return;
-            a.pair_key[o] = pair_key(a, tx, ty, i0, i1, j0, j1);
+            a.pair_key[o] = pair_key(a, tx, ty, i0, i1, j0, j1, bb.y);
             a.pair_val[o] = i;
             ++o;
         }
@@ -162,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_emit_waves(EmitArgs a) {
         const uint32_t nx = (uint32_t)(i1 / T - tx0 + 1);
         const uint32_t row = t / nx;
         const int tx = tx0 + (int)(t - row * nx), ty = ty0 + (int)row;
-        a.pair_key[slot] = pair_key(a, tx, ty, i0, i1, j0, j1);
+        a.pair_key[slot] = pair_key(a, tx, ty, i0, i1, j0, j1, b1);
         a.pair_val[slot] = s_idx[e];
     }
 }
@@ -200,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_emit_split(EmitArgs a, uint32_t nb
         for (uint32_t t = lane; t < c; t += 64) {
             if (o + t >= a.cap) break;
             const int tx = tx0 + (int)(t % (uint32_t)nx), ty = ty0 + (int)(t / (uint32_t)nx);
-            a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1);
+            a.pair_key[o + t] = pair_key(a, tx, ty, i0, i1, j0, j1, bb.y);
             a.pair_val[o + t] = i;
         }
     }

@@ -10,6 +10,10 @@ namespace splotch {
 constexpr int kMaxSpecies = 8;
 constexpr int kBboxBits = 14;  // i0, i1 packed in 14 bits each (W, H <= 16384)
 constexpr uint32_t kBboxMask = (1u << kBboxBits) - 1u;
+// Bits 28..31 of a record's second word (above j0, j1): whether the box's
+// corner 8x8 block (lowest or highest block column, lowest or highest block
+// row: bit 28 + (x high) + 2 (y high)) holds no pixel within the radius.
+constexpr int kCornerShift = 28;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 
 // Status codes written per particle by the projection kernel.

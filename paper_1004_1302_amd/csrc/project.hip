@@ -96,6 +96,45 @@ __device__ Proj project_spec(const CamDev &c, float x, float y, float z, float h
     return p;
 }
 
+// Along one axis, the squared offset the splat's row walk computes between
+// the footprint's centre c (relative to the box origin o) and the nearest
+// pixel centre of lo..hi, or 0 when that range holds the pixel pc at or
+// left of c or the next one.  dx = fl((p - o + 0.5) - c) grows with p, so a
+// range on one side of c is nearest at its edge on c's side (pc comes from
+// floor(c - 0.5), whose rounding can only put it one pixel right).
+__device__ __forceinline__ float axis_gap2(int lo, int hi, int o, int pc, float c) {
+#pragma clang fp contract(off)
+    if (lo <= pc + 1 && pc <= hi) return 0.0f;
+    const int p = hi < pc ? hi : lo;
+    const float g = __builtin_fmaf(0.5f, (float)(2 * (p - o) + 1), -c);
+    return g * g;
+}
+
+// The corner bits of a record: which of the box's four corner 8x8 blocks
+// (when it spans two block columns and rows or more) lie off the centre's
+// block row and column with even their nearest pixel outside the radius by
+// the row walk's own rounded distance (dx dx + dy dy, each step rounded).
+// That distance is no larger there than at the block's other pixels, so
+// the row walk would find no member in such a block.
+__device__ __forceinline__ uint32_t corner_bits(const Proj &p) {
+#pragma clang fp contract(off)
+    const int bc0 = p.i0 >> 3, bc1 = p.i1 >> 3, br0 = p.j0 >> 3, br1 = p.j1 >> 3;
+    if (bc1 == bc0 || br1 == br0) return 0u;
+    const int pcx = p.i0 + (int)floorf(p.ur - 0.5f), pcy = p.j0 + (int)floorf(p.vr - 0.5f);
+    const float gx[2] = {axis_gap2(p.i0, min(p.i1, 8 * bc0 + 7), p.i0, pcx, p.ur),
+                         axis_gap2(max(p.i0, 8 * bc1), p.i1, p.i0, pcx, p.ur)};
+    const float gy[2] = {axis_gap2(p.j0, min(p.j1, 8 * br0 + 7), p.j0, pcy, p.vr),
+                         axis_gap2(max(p.j0, 8 * br1), p.j1, p.j0, pcy, p.vr)};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int yh = 0; yh < 2; ++yh)
+#pragma unroll
+        for (int xh = 0; xh < 2; ++xh)
+            if (gx[xh] != 0.0f && gy[yh] != 0.0f && gx[xh] + gy[yh] > p.r2)
+                bits |= 1u << (xh + 2 * yh);
+    return bits;
+}
+
 __device__ __forceinline__ bool particle_valid(float x, float y, float z, float h, float v,
                                                float r0, int sp, int ns) {
     return finite_f(x) && finite_f(y) && finite_f(z) && finite_f(h) && finite_f(v) &&
@@ -198,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_project(ProjectArgs a) {
             float qsf = (float)fmin(qs, (double)FLT_MAX);
             Rec r;
             r.a.x = (uint32_t)p.i0 | ((uint32_t)p.i1 << kBboxBits) | ((uint32_t)sp << 28);
-            r.a.y = (uint32_t)p.j0 | ((uint32_t)p.j1 << kBboxBits);
+            r.a.y = (uint32_t)p.j0 | ((uint32_t)p.j1 << kBboxBits) | (corner_bits(p) << kCornerShift);
             r.a.z = __float_as_uint(p.ur);
             r.a.w = __float_as_uint(p.vr);
             r.b.x = __float_as_uint(p.r2);
