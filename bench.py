@@ -125,9 +125,9 @@ def cpu_baseline(parts, cam, sp, args, np, torch):
     """The FP64 oracle timed on the host cores: row bands of the image
     painted by all OpenMP threads (the same image as the single-thread
     definition, bit for bit).  Sets above 1e7 particles are timed on a
-    seeded random subsample (--cpu-fraction, default 1/1000: the full set
-    in FP64 does not fit host memory) and the per-particle rate is
-    extrapolated; smaller sets are timed whole."""
+    seeded random subsample (--cpu-fraction, default 1/50: about 8 s a run
+    on 16 threads, where the full set in FP64 would not fit host memory) and
+    the per-particle rate is extrapolated; smaller sets are timed whole."""
     import oracle
     n = int(parts["x"].numel())
     frac = 1.0 if n <= 10_000_000 else float(args.cpu_fraction)
@@ -204,7 +204,7 @@ def main():
     ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--splat-variant", type=int, default=0)
     ap.add_argument("--max-pairs", type=float, default=0)
-    ap.add_argument("--cpu-fraction", type=float, default=1e-3)
+    ap.add_argument("--cpu-fraction", type=float, default=0.02)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
