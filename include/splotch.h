@@ -194,7 +194,8 @@ typedef struct splotch_params {
                             0 = default (1);
                             1 = one lane per pixel: the wave of each 8x8
                                 block walks the records whose box meets
-                                its block;
+                                its block (less a box's corner blocks
+                                that hold no pixel within the radius);
                             2 = one lane per pixel: each lane first lists
                                 its member records, then composites them;
                             3 = one wave per tile, pixel state in LDS, the

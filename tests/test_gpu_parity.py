@@ -326,6 +326,56 @@ def test_block_masks_on_and_off_bitwise_equal(torch_cuda):
                 same_composite(one(scene, tile, compensated), ref, compensated, (w, tile))
 
 
+def corner_scene(n=30_000, seed=19, w=256):
+    """Footprints centred near the corners where four 8x8 blocks meet, with
+    radii that put the circle at, just inside or just outside the nearest
+    pixel centre of the diagonal block: the cases where a box's corner block
+    is left out of a pair's block mask or kept by one rounding."""
+    rng = np.random.default_rng(seed)
+    cam = synth.ortho_unit_square(w, w)
+    cx = 8.0 * rng.integers(2, w // 8 - 2, n) + rng.choice([-1.5, -0.75, -0.5, 0.0, 0.25, 0.5, 1.0], n)
+    cy = 8.0 * rng.integers(2, w // 8 - 2, n) + rng.choice([-1.25, -0.5, 0.0, 0.5, 0.75, 1.5], n)
+    # distance to the nearest pixel centre across the block corner (8a, 8b)
+    dx = np.abs(np.round(cx / 8.0) * 8.0 + np.where(cx < np.round(cx / 8.0) * 8.0, 0.5, -0.5) - cx)
+    dy = np.abs(np.round(cy / 8.0) * 8.0 + np.where(cy < np.round(cy / 8.0) * 8.0, 0.5, -0.5) - cy)
+    d = np.hypot(dx, dy)
+    r = d * rng.choice([1.0 - 1e-3, 1.0 - 1e-7, 1.0, 1.0 + 1e-7, 1.0 + 1e-3, 1.6], n)
+    r = np.maximum(r, 0.3)
+    sc = synth.Scene((cx / w).astype(np.float32), (cy / w).astype(np.float32),
+                     rng.uniform(0.0, 1.0, n).astype(np.float32),
+                     (r / (2.0 * w)).astype(np.float32),  # trunc_f 2, sigma_over_h 1
+                     rng.lognormal(0, 1, n).astype(np.float32), cam,
+                     [synth.Species(log_scale=1, brightness=0.5, absorption=0.5,
+                                    mode=synth.ORDERED),
+                      synth.Species(brightness=0.4, mode=synth.ADDITIVE)],
+                     species=rng.integers(0, 2, n).astype(np.uint8), name="corners")
+    return sc
+
+
+def test_corner_blocks_left_out_keep_every_member(torch_cuda, orc):
+    """A pair's block mask leaves out the box's corner blocks whose nearest
+    pixel is outside the radius by the row walk's own rounding.  With
+    footprints placed on block corners at the threshold, renders with the
+    masks (16 and 32 px tiles) match the unmasked 8 px tiles bit for bit
+    without compensation, and every render matches the oracle."""
+    scene = corner_scene()
+    ref = orc.render(scene)
+
+    def one(tile, compensated):
+        img, st = gpu_render(scene, tile=tile, compensated=compensated, seg_records=1 << 24,
+                             splat_variant=1, max_pairs=1 << 24, stats=True)
+        assert st["n_chunks"] == 1
+        return img
+
+    for compensated in (False, True):
+        base = one(8, compensated)
+        check_image(base, ref)
+        for tile in (16, 32):
+            img = one(tile, compensated)
+            same_composite(img, base, compensated, ("corners", tile))
+            check_image(img, ref)
+
+
 @pytest.mark.parametrize("spread", [0.0, 1e-6, 0.25])
 def test_depth_sort_over_the_visible_key_span(torch_cuda, orc, spread):
     """The depth sort runs only over the digits the visible depth keys span:
