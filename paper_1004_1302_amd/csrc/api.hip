@@ -1093,7 +1093,6 @@ splotch_status splotch_render_batch(const splotch_particles *P, int32_t n_views,
     q.workspace_bytes = p->workspace_bytes / (size_t)K / 256 * 256;  // one lane's part
     if ((st = prepare(P, &cams[big], &q, &c)) != SPLOTCH_OK) return st;
     if (use_graph && c.s == nullptr) return SPLOTCH_E_INVALID_ARG;
-    TRY(radix_prepare_stride_grids());
     std::lock_guard<std::mutex> lane_lock(g_lane_mu);
     LaneSet *ls = nullptr;
     std::vector<Ctx> lanes(K);

@@ -133,9 +133,6 @@ hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *
                             uint32_t bias, bool keys_needed, void *scratch, bool *result_in_1,
                             hipStream_t s, const uint32_t *tag_counts = nullptr,
                             const uint32_t *key_range = nullptr);
-// Look up (once per device) the grids of the passes that take their count
-// on the device, so that no occupancy query runs under graph capture.
-hipError_t radix_prepare_stride_grids();
 constexpr int kTagShift = 30;
 constexpr uint32_t kIdxMask = (1u << kTagShift) - 1u;
 // Exclusive scan of the counts a tagged order carries (cnt: counts by

@@ -8,7 +8,6 @@
 // (wave ballots find equal digits, lanes in order, waves in order: stable),
 // reorders the tile in LDS and writes each digit run contiguously.
 #include <algorithm>
-#include <atomic>
 
 #include "internal.h"
 
@@ -20,7 +19,6 @@ constexpr int kT = 256;
 constexpr int kW = kT / 64;
 constexpr int kIpt = 16;
 constexpr int kTile = kT * kIpt;  // 4096
-constexpr int kMaxDevices = 64;        // striding grids cached per device
 
 __device__ __forceinline__ uint32_t shfl_up_u32(uint32_t v, int o) {
     return (uint32_t)__shfl_up((int)v, o, 64);
@@ -250,13 +248,11 @@ __device__ __forceinline__ uint32_t tag_value(uint32_t idx, uint32_t count) {
     return idx | (code << kTagShift);
 }
 
-// Tiles of a radix pass.  With the element count known on the host the
-// grid has one workgroup per tile.  With a count on the device (batched
-// views: the pair arrays are sized to their capacity) the grid is capped
-// and each workgroup strides over the tiles; the live tiles are those the
-// device count fills, and the XCD-contiguous order is taken over them, so
-// every XCD shares the live work.  The capacity's other tiles need only
-// zero histogram columns.
+// Tiles of a radix pass: one workgroup per tile.  With a count on the
+// device (batched views: the pair arrays are sized to their capacity) the
+// live tiles are those the device count fills, and the XCD-contiguous
+// order is taken over them, so every XCD shares the live work; the
+// capacity's other workgroups write zero histogram columns or return.
 struct PassTiles {
     uint32_t live;  // tiles holding elements
     uint32_t all;   // tiles of the capacity (the histogram's columns)
@@ -265,7 +261,7 @@ struct PassTiles {
         live = t < nblocks ? (uint32_t)t : nblocks;
         all = nblocks;
     }
-    // tile of stride position b (b < live: XCD-contiguous among the live)
+    // tile of workgroup b (b < live: XCD-contiguous among the live)
     __device__ uint32_t tile(uint32_t b) const {
         return b < live ? xcd_contiguous(b, live) : b;
     }
@@ -299,10 +295,9 @@ struct DeviceKeys {
 // keep a wave whose keys share a digit from serialising on one LDS address.
 constexpr int kHistCopies = 16;
 
-// STRIDE: the grid strides over the tiles (a count on the device); else one
-// workgroup per tile.
-// DB: digit bits (7 or 8): the histogram has 2^DB columns per tile.
-template <bool STRIDE, int DB>
+// One workgroup per tile of the capacity.  DB: digit bits (7 or 8): the
+// histogram has 2^DB columns per tile.
+template <int DB>
 __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_cap,
                                                 const uint64_t *n_dev, int shift, uint32_t bias,
                                                 uint32_t *hist, uint32_t nblocks, DeviceKeys dk) {
@@ -315,30 +310,27 @@ __global__ __launch_bounds__(kT) void k_rs_hist(const uint32_t *keys, size_t n_c
     const PassTiles pt(n, nblocks);
     __shared__ uint32_t sh[kHistCopies][ND];
     const int c = threadIdx.x & (kHistCopies - 1);
-    for (uint32_t b = blockIdx.x; b < pt.all; b += STRIDE ? gridDim.x : pt.all) {
-        // neighbouring tiles' counts share lines of the digit-major histogram
-        const uint32_t t = pt.tile(b);
-        if (b >= pt.live) {
-            if (threadIdx.x < ND) hist[(size_t)threadIdx.x * nblocks + t] = 0u;
-            continue;
-        }
-        for (int d = threadIdx.x; d < kHistCopies * (int)ND; d += kT) (&sh[0][0])[d] = 0;
-        __syncthreads();
-        const size_t base = (size_t)t * kTile;
+    // neighbouring tiles' counts share lines of the digit-major histogram
+    const uint32_t b = blockIdx.x;
+    const uint32_t t = pt.tile(b);
+    if (b >= pt.live) {
+        if (threadIdx.x < ND) hist[(size_t)threadIdx.x * nblocks + t] = 0u;
+        return;
+    }
+    for (int d = threadIdx.x; d < kHistCopies * (int)ND; d += kT) (&sh[0][0])[d] = 0;
+    __syncthreads();
+    const size_t base = (size_t)t * kTile;
 #pragma unroll
-        for (int q = 0; q < kIpt; ++q) {
-            size_t idx = base + (size_t)q * kT + threadIdx.x;
-            if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & DM], 1u);
-        }
-        __syncthreads();
-        if (threadIdx.x < ND) {
-            uint32_t sum = 0;
+    for (int q = 0; q < kIpt; ++q) {
+        size_t idx = base + (size_t)q * kT + threadIdx.x;
+        if (idx < n) atomicAdd(&sh[c][((keys[idx] - bias) >> shift) & DM], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < ND) {
+        uint32_t sum = 0;
 #pragma unroll
-            for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
-            hist[(size_t)threadIdx.x * nblocks + t] = sum;
-        }
-        if (!STRIDE) break;
-        __syncthreads();  // before the next tile clears the counters
+        for (int k = 0; k < kHistCopies; ++k) sum += sh[k][threadIdx.x];
+        hist[(size_t)threadIdx.x * nblocks + t] = sum;
     }
 }
 
@@ -439,7 +431,7 @@ __device__ __forceinline__ void scatter_tile(ScatterLds<DB> &L, uint32_t t, size
     }
 }
 
-template <bool STRIDE, int DB>
+template <int DB>
 __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const uint32_t *vin,
                                                    uint32_t *kout, uint32_t *vout, size_t n_cap,
                                                    const uint64_t *n_dev, int shift,
@@ -455,21 +447,13 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
         vout = ((passes - 1 - dk.slot) & 1) ? dk.v1 : dk.v0;
         if (dk.slot == passes - 1) write_keys = 0;
     }
-    // the runs two neighbouring tiles write for one digit are adjacent in
-    // the output
-    if (!STRIDE) {
-        const uint32_t t = xcd_contiguous(blockIdx.x, nblocks);
-        if ((size_t)t * kTile < n)
-            scatter_tile(L, t, n, kin, vin, kout, vout, shift, bias, hist, nblocks, write_keys,
-                         tag);
-        return;
-    }
+    // one workgroup per tile of the capacity; those past the live tiles (a
+    // count on the device) return at once.  The runs two neighbouring tiles
+    // write for one digit are adjacent in the output.
     const PassTiles pt(n, nblocks);
-    for (uint32_t b = blockIdx.x; b < pt.live; b += gridDim.x) {
-        scatter_tile(L, pt.tile(b), n, kin, vin, kout, vout, shift, bias, hist, nblocks,
+    if (blockIdx.x < pt.live)
+        scatter_tile(L, pt.tile(blockIdx.x), n, kin, vin, kout, vout, shift, bias, hist, nblocks,
                      write_keys, tag);
-        __syncthreads();  // before the next tile reuses the LDS
-    }
 }
 
 }  // namespace
@@ -506,75 +490,20 @@ size_t radix_scratch_bytes(size_t n) {
     return hist + scan_u32_scratch_bytes(nb * 256);
 }
 
-// Workgroups of a striding pass: as many as the device holds at once (a
-// multiple of 8, so each keeps its XCD).  A larger grid would leave its
-// last workgroups waiting for the first to finish their whole stride: the
-// scatter's LDS allows 4 workgroups per CU, 1024 on the device.  Cached per
-// device and kernel; 0 when the runtime cannot tell.
-template <typename K>
-uint32_t resident_grid(K kernel, std::atomic<uint32_t> *cache) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
-    uint32_t g = cache[dev].load(std::memory_order_relaxed);
-    if (g) return g;
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kT, 0) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    g = (uint32_t)std::max(per_cu, 1) * (uint32_t)std::max(cus, 1);
-    g = std::max<uint32_t>(g / 8 * 8, 8);
-    cache[dev].store(g, std::memory_order_relaxed);
-    return g;
-}
-
-// One pass: digit histogram per tile, its scan, the scatter.
-struct StrideGrids {
-    uint32_t hist, scatter;
-};
-
-template <int DB>
-StrideGrids stride_grids() {
-    static std::atomic<uint32_t> hist_grid[kMaxDevices], scatter_grid[kMaxDevices];
-    return StrideGrids{resident_grid(k_rs_hist<true, DB>, hist_grid),
-                       resident_grid(k_rs_scatter<true, DB>, scatter_grid)};
-}
-
+// One pass: digit histogram per tile, its scan, the scatter.  A count on
+// the device (n_dev) bounds the live tiles; the grid covers the capacity.
 template <int DB>
 hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
                       size_t n, const uint64_t *n_dev, int shift, uint32_t bias, uint32_t *hist,
                       uint32_t nb, int write_keys, const uint32_t *tag, DeviceKeys dk,
                       void *scan_scratch, hipStream_t s) {
-    const StrideGrids sg = n_dev ? stride_grids<DB>() : StrideGrids{0, 0};
-    if (n_dev) {
-        // a count on the device: a grid of resident workgroups striding over
-        // the live tiles
-        const uint32_t g = sg.hist;
-        if (!g) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_rs_hist<true, DB>), dim3(std::min(nb, g)), dim3(kT), 0, s, kin, n,
-                           n_dev, shift, bias, hist, nb, dk);
-    } else {
-        hipLaunchKernelGGL((k_rs_hist<false, DB>), dim3(nb), dim3(kT), 0, s, kin, n, n_dev,
-                           shift, bias, hist, nb, dk);
-    }
+    hipLaunchKernelGGL((k_rs_hist<DB>), dim3(nb), dim3(kT), 0, s, kin, n, n_dev, shift, bias, hist,
+                       nb, dk);
     hipError_t e = launch_scan_u32(hist, (size_t)nb << DB, scan_scratch, s);
     if (e != hipSuccess) return e;
-    if (n_dev) {
-        const uint32_t g = sg.scatter;
-        if (!g) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_rs_scatter<true, DB>), dim3(std::min(nb, g)), dim3(kT), 0, s, kin,
-                           vin, kout, vout, n, n_dev, shift, bias, hist, nb, write_keys, tag, dk);
-    } else {
-        hipLaunchKernelGGL((k_rs_scatter<false, DB>), dim3(nb), dim3(kT), 0, s, kin, vin, kout,
-                           vout, n, n_dev, shift, bias, hist, nb, write_keys, tag, dk);
-    }
+    hipLaunchKernelGGL((k_rs_scatter<DB>), dim3(nb), dim3(kT), 0, s, kin, vin, kout, vout, n,
+                       n_dev, shift, bias, hist, nb, write_keys, tag, dk);
     return hipGetLastError();
-}
-
-hipError_t radix_prepare_stride_grids() {
-    return stride_grids<7>().hist && stride_grids<7>().scatter && stride_grids<8>().hist &&
-                   stride_grids<8>().scatter
-               ? hipSuccess
-               : hipErrorInvalidValue;
 }
 
 hipError_t radix_sort_pairs(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1,
