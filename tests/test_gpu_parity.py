@@ -409,6 +409,40 @@ def test_depth_sort_over_the_visible_key_span(torch_cuda, orc, spread):
     assert npairs == ep.size
     assert np.array_equal(pp.cpu().numpy().view(np.uint32).astype(np.int64), ep)
     check_image(gpu_render(scene), orc.render(scene))
+    # A batch reads nothing back: its depth passes take the key range from
+    # the device and return past its digits; the images are the single
+    # render's bits.
+    for compensated in (False, True):
+        kw = dict(sigma_over_h=scene.sigma_over_h, trunc_f=scene.trunc_f, tile=16,
+                  compensated=compensated)
+        one = B.render(parts, scene.camera, pal, scene.species_params, **kw).cpu().numpy()
+        for streams in (1, 2):
+            imgs = B.render_batch(parts, [scene.camera, scene.camera], pal,
+                                  scene.species_params, streams=streams, **kw)
+            for im in imgs:
+                assert np.array_equal(im.cpu().numpy(), one), (spread, compensated, streams)
+
+
+def test_batch_with_nothing_visible(torch_cuda):
+    """Every particle behind the camera: the depth-key range on the device is
+    empty (smallest above largest), the batch's one sorting pass orders
+    nothing, and the images stay black like the single render's."""
+    rng = np.random.default_rng(5)
+    n = 5_000
+    cam = synth.ortho_unit_square(64, 48)
+    sp = [synth.Species(log_scale=1, brightness=0.4, absorption=0.6, mode=synth.ORDERED)]
+    scene = synth.Scene(rng.uniform(0, 1, n).astype(np.float32),
+                        rng.uniform(0, 1, n).astype(np.float32),
+                        np.full(n, -3.0, np.float32),
+                        np.full(n, 0.02, np.float32), np.ones(n, np.float32), cam, sp)
+    parts, pal = B.scene_to_device(scene)
+    one = B.render(parts, cam, pal, scene.species_params, tile=16).cpu().numpy()
+    assert not np.any(one)
+    imgs, st = B.render_batch(parts, [cam, cam], pal, scene.species_params, tile=16, streams=2,
+                              stats=True)
+    assert all(v["n_pairs"] == 0 for v in st)
+    for im in imgs:
+        assert np.array_equal(im.cpu().numpy(), one)
 
 
 def test_edges_ordered_with_background(torch_cuda, orc):
