@@ -423,6 +423,34 @@ def test_depth_sort_over_the_visible_key_span(torch_cuda, orc, spread):
                 assert np.array_equal(im.cpu().numpy(), one), (spread, compensated, streams)
 
 
+@pytest.mark.parametrize("n", [4096, 16384, 16385, 20480, 20481])
+def test_scans_around_the_one_workgroup_size(torch_cuda, orc, n):
+    """Scans of at most four 4096-element tiles run in one workgroup, longer
+    ones in three kernels: particle counts at and just past both sizes give
+    bit-exact pair lists (the pair offsets are a scan over the particles)."""
+    rng = np.random.default_rng(n)
+    cam = synth.ortho_unit_square(80, 64)
+    sp = [synth.Species(log_scale=1, brightness=0.4, absorption=0.6, mode=synth.ORDERED),
+          synth.Species(brightness=0.3, mode=synth.ADDITIVE)]
+    scene = synth.Scene(rng.uniform(0, 1, n).astype(np.float32),
+                        rng.uniform(0, 1, n).astype(np.float32),
+                        rng.uniform(0, 1, n).astype(np.float32),
+                        rng.lognormal(np.log(0.03), 0.6, n).astype(np.float32),
+                        rng.lognormal(0, 1, n).astype(np.float32), cam, sp,
+                        species=rng.integers(0, 2, n).astype(np.uint8))
+    parts, pal = B.scene_to_device(scene)
+    ts, te, pp, npairs = B.bin_pairs(parts, scene.camera, scene.species_params,
+                                      sigma_over_h=scene.sigma_over_h, trunc_f=scene.trunc_f,
+                                      tile=16)
+    ref = orc.project(scene, tile=16)
+    es, ee, ep = expected_bins(ref, scene, 16, True)
+    assert npairs == ep.size
+    assert np.array_equal(pp.cpu().numpy().view(np.uint32).astype(np.int64), ep)
+    assert np.array_equal(ts.cpu().numpy().astype(np.int64), es)
+    assert np.array_equal(te.cpu().numpy().astype(np.int64), ee)
+    check_image(gpu_render(scene, compensated=True), orc.render(scene))
+
+
 def test_batch_with_nothing_visible(torch_cuda):
     """Every particle behind the camera: the depth-key range on the device is
     empty (smallest above largest), the batch's one sorting pass orders
