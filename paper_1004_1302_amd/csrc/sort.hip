@@ -215,6 +215,17 @@ __global__ void k_set_value(TO *p, TO v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Partials one workgroup scans in turn; more than that are scanned by the
+// same three kernels (one level down), which the scratch then also holds.
+constexpr size_t kPartialsOneGroup = 16 * 1024;
+
+size_t scan_scratch_words(size_t n) {
+    const size_t nb = (n + kTile - 1) / kTile;
+    size_t w = nb + 1;
+    if (nb > kPartialsOneGroup) w += scan_scratch_words(nb);
+    return w;
+}
+
 template <typename L, typename TO>
 hipError_t scan_impl(L in, TO *out, size_t n, TO *total_out, void *scratch, hipStream_t s) {
     if (n == 0) {
@@ -229,7 +240,15 @@ hipError_t scan_impl(L in, TO *out, size_t n, TO *total_out, void *scratch, hipS
     TO *partial = reinterpret_cast<TO *>(scratch);
     hipLaunchKernelGGL((k_scan_reduce<L, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, n,
                        partial);
-    hipLaunchKernelGGL(k_scan_partials<TO>, dim3(1), dim3(1024), 0, s, partial, nb, total_out);
+    if (nb > kPartialsOneGroup) {
+        // the partials' exclusive scan in place, its own partials after them
+        hipError_t e = scan_impl<LoadPlain<TO>, TO>(LoadPlain<TO>{partial}, partial, nb, total_out,
+                                                    partial + nb + 1, s);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_scan_partials<TO>, dim3(1), dim3(1024), 0, s, partial, nb,
+                           total_out);
+    }
     hipLaunchKernelGGL((k_scan_down<L, TO>), dim3((unsigned)nb), dim3(kT), 0, s, in, out, n,
                        partial);
     return hipGetLastError();
@@ -459,7 +478,7 @@ __global__ __launch_bounds__(kT) void k_rs_scatter(const uint32_t *kin, const ui
 }  // namespace
 
 size_t scan_u32_u64_scratch_bytes(size_t n) {
-    return align_up(((n + kTile - 1) / kTile + 1) * sizeof(uint64_t), 256);
+    return align_up(scan_scratch_words(n) * sizeof(uint64_t), 256);
 }
 
 hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void *scratch,
@@ -475,7 +494,7 @@ hipError_t launch_scan_tagged_counts(const uint32_t *order, const uint32_t *cnt,
 }
 
 size_t scan_u32_scratch_bytes(size_t n) {
-    return align_up(((n + kTile - 1) / kTile + 1) * sizeof(uint32_t), 256);
+    return align_up(scan_scratch_words(n) * sizeof(uint32_t), 256);
 }
 
 hipError_t launch_scan_u32(uint32_t *data, size_t n, void *scratch, hipStream_t s) {
